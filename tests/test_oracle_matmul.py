@@ -1,0 +1,120 @@
+"""The oracle's encrypted products decrypt to the plain FP64 definition X y
+(or A W) within the precision budget.  CPU only."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import plans as PL
+from paper_2405_00482_amd import workloads as W
+
+
+def rel_err(got, ref):
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def tiny(logN, nq, npr, scale_bits=30, q0_bits=40):
+    N = 1 << logN
+    out = []
+    for bits, cnt in ((q0_bits, 1), (40, nq - 1), (48, npr)):
+        x = ((1 << bits) - 1) // (2 * N) * (2 * N) + 1
+        got = 0
+        while got < cnt:
+            if O.is_prime(x) and x not in out:
+                out.append(x)
+                got += 1
+            x -= 2 * N
+    return O.Params(logN=logN, q=out[:nq], p=out[nq:], log2_scale=float(scale_bits))
+
+
+def run_hybrid(prm, X, y, lazy, seed=1):
+    N = prm.N
+    plan = PL.HybridPlan(X.shape[0], X.shape[1], prm.slots)
+    s = O.keygen(prm, seed)
+    keys = {g: O.rotkey_gen(prm, s, g, seed + 1) for g in PL.hybrid_galois(plan, N)}
+    cts = [O.encrypt(prm, s, m, prm.L, seed + 2 + c) for c, m in enumerate(PL.hybrid_ct_ints(prm, plan, y, prm.scale))]
+    pts = PL.hybrid_pt_ints(prm, plan, X, prm.scale)
+    outs = PL.hybrid_matmul(prm, plan, cts, pts, keys, lazy)
+    zs = [O.decrypt_decode(prm, s, ct, prm.scale * prm.scale) for ct in outs]
+    return PL.hybrid_lazy_ras(plan, zs)
+
+
+@pytest.mark.parametrize("lazy", [True, False])
+def test_c1_hybrid_precision(lazy):
+    """C1: ring 2^12, Delta 2^30, X^T 16x256 times [[r]]; 2^-20 norm-wise gate for
+    the lazy-ModDown plan (the eager plan's extra rounding noise is reported)."""
+    prm = O.Params.from_dict(W.params_dict("C1"))
+    XT, r = W.c1_inputs()
+    got = run_hybrid(prm, XT, r, lazy)
+    err = rel_err(got, XT @ r)
+    bound = 2.0 ** -20 if lazy else 2.0 ** -18
+    assert err < bound, err
+
+
+@pytest.mark.parametrize("m,n,logN", [(64, 8, 5), (8, 64, 5), (32, 64, 5), (5, 3, 5)])
+def test_partitioned_hybrid(m, n, logN):
+    prm = tiny(logN, 2, 1)
+    rng = np.random.default_rng(m * n)
+    X = rng.uniform(-1, 1, (m, n))
+    y = rng.uniform(-1, 1, n)
+    for lazy in (True, False):
+        assert rel_err(run_hybrid(prm, X, y, lazy), X @ y) < 1e-3
+
+
+@pytest.mark.parametrize("m,n", [(16, 4), (4, 16)])
+def test_diag_plan(m, n):
+    prm = tiny(5, 2, 1)
+    N = prm.N
+    rng = np.random.default_rng(3)
+    X = rng.uniform(-1, 1, (m, n))
+    y = rng.uniform(-1, 1, n)
+    s = O.keygen(prm, 4)
+    for ras in ("lazy", "rot"):
+        plan = PL.DiagPlan(m, n, prm.slots, ras)
+        keys = {g: O.rotkey_gen(prm, s, g, 5) for g in PL.diag_galois(plan, N)}
+        ct = O.encrypt(prm, s, O.encode(PL.diag_ct_slots(plan, y), N, prm.scale), prm.L, 6)
+        pts = [O.encode(PL.diag_pt_slots(plan, X, i), N, prm.scale) for i in range(plan.ndiag)]
+        out = PL.diag_matmul(prm, plan, ct, pts, keys, lazy=False)
+        z = O.decrypt_decode(prm, s, out, prm.scale ** 2)
+        assert rel_err(PL.diag_finish(plan, z), X @ y) < 1e-3
+
+
+def test_row_plan_two_rescales():
+    prm = tiny(5, 3, 1, scale_bits=30, q0_bits=45)
+    N = prm.N
+    rng = np.random.default_rng(4)
+    m, n = 6, 8
+    X = rng.uniform(-1, 1, (m, n))
+    y = rng.uniform(-1, 1, n)
+    plan = PL.RowPlan(m, n, prm.slots)
+    s = O.keygen(prm, 7)
+    keys = {g: O.rotkey_gen(prm, s, g, 8) for g in PL.row_galois(plan, N)}
+    ct_slots = np.zeros(prm.slots)
+    for t in range(prm.slots):
+        ct_slots[t] = y[t % plan.np_] if t % plan.np_ < n else 0.0
+    ct = O.encrypt(prm, s, O.encode(ct_slots, N, prm.scale), prm.L, 9)
+    pts = [O.encode(PL.row_pt_slots(plan, X, r), N, prm.scale) for r in range(m)]
+    ind = np.zeros(prm.slots)
+    ind[0] = 1.0
+    ind_ints = O.encode(ind, N, float(prm.q[1]))
+    out = PL.row_matmul(prm, plan, ct, pts, ind_ints, keys)
+    assert out.level == 0
+    z = O.decrypt_decode(prm, s, out, prm.scale ** 2 / prm.q[2])
+    assert rel_err(z[:m], X @ y) < 1e-3
+
+
+@pytest.mark.parametrize("pack", [1, 2])
+def test_ctmat_plan(pack):
+    prm = tiny(5, 2, 1)
+    N = prm.N
+    rng = np.random.default_rng(5)
+    A = rng.uniform(-1, 1, (8, 4))
+    Wm = rng.normal(0, 0.1, (4, 3))
+    plan = PL.CtMatPlan(8, 4, 3, prm.slots, pack)
+    s = O.keygen(prm, 2)
+    cts = [O.encrypt(prm, s, O.encode(PL.ctmat_ct_slots(plan, A, i), N, prm.scale), prm.L, 30 + i)
+           for i in range(plan.ndiag)]
+    pts = [O.encode(PL.ctmat_pt_slots(plan, Wm, i, k), N, prm.scale)
+           for i in range(plan.ndiag) for k in range(plan.n_out_cts)]
+    outs = PL.ctmat_matmul(prm, plan, cts, pts)
+    zs = [O.decrypt_decode(prm, s, c, prm.scale ** 2) for c in outs]
+    assert rel_err(PL.ctmat_finish(plan, zs), A @ Wm) < 1e-3
