@@ -1,0 +1,180 @@
+/*
+ * pvfl.h -- C ABI of the MI355X (gfx950) library for the packed-HE
+ * ciphertext x plaintext matrix product of PackVFL (arXiv 2405.00482).
+ *
+ * Problem statement (Sec. 3, Eq. 1): a party holding the plaintext matrix X
+ * computes X [[y]] = [[X y]] on a vector y that the key owner encrypted; the
+ * result goes back to the key owner, who only decrypts it (characteristic C3,
+ * Sec. 4).  The matrix form [[A]] W of Alg. 3 (Sec. 5.3) is also supported.
+ * The encryption is RNS-CKKS (the paper's implementation uses Lattigo CKKS,
+ * Sec. 6) with hybrid key switching.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: every call returns pvfl_status (0 = OK, < 0 = error) and never
+ *   throws; pvfl_last_error() returns a message for the calling thread.
+ * - Arguments are validated (shapes, levels, key coverage) before any work is
+ *   enqueued; on error nothing is launched.
+ * - Device buffers ("_dev") are caller-owned device memory (e.g. from
+ *   torch), sized with the pvfl_bytes_* queries; the library never frees them.
+ *   Host arrays are only read during the call.  Handles (pvfl_ctx, pvfl_sk,
+ *   pvfl_rotkeys, pvfl_plan) are opaque, owned by the library, and released
+ *   with the matching destroy call; destroying a handle twice is undefined.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *   work is enqueued on it and the call returns without waiting, except the
+ *   handle-creating calls, which synchronise.
+ * - Residue storage.  A "poly" of L limbs is double[L][N]: limb i holds the
+ *   residues modulo prime i of the basis, each an integer held exactly in an
+ *   IEEE-754 binary64 with |x| <= q_i, in the evaluation (NTT) domain, in the
+ *   slot-orbit order (index t is the evaluation at psi^(5^t) for t < N/2 and
+ *   at psi^(-5^(t-N/2)) otherwise).  A ciphertext at level l is double[2][l+1][N]
+ *   (c0 then c1).  Basis order: q_0..q_l, then the special primes p_0..p_{a-1}.
+ *   Use pvfl_export_coeffs to read residues back as canonical uint64
+ *   coefficient-domain values.
+ * - All primes must be below 2^49 and congruent to 1 mod 2N.
+ */
+#ifndef PVFL_H
+#define PVFL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PVFL_OK = 0,
+  PVFL_E_INVALID = -1, /* bad argument or parameter set */
+  PVFL_E_SHAPE = -2,   /* shape or buffer size does not match the plan */
+  PVFL_E_LEVEL = -3,   /* ciphertext level too low for the plan */
+  PVFL_E_NOKEY = -4,   /* a rotation key the plan needs is missing */
+  PVFL_E_NOMEM = -5,   /* device allocation failed */
+  PVFL_E_DEVICE = -6,  /* HIP runtime error */
+  PVFL_E_PLAN = -7     /* plan kind cannot serve this request */
+} pvfl_status;
+
+typedef struct pvfl_ctx pvfl_ctx;
+typedef struct pvfl_sk pvfl_sk;
+typedef struct pvfl_rotkeys pvfl_rotkeys;
+typedef struct pvfl_plan pvfl_plan;
+
+/* RNS-CKKS parameter set.  q: n_q ciphertext primes (level L = n_q - 1);
+ * p: n_p special primes of the key-switching modulus P (alpha = n_p, so the
+ * digit count at level l is ceil((l+1)/alpha)).  Copied by the library. */
+typedef struct {
+  uint32_t log_n;      /* ring degree N = 2^log_n, 12..14 */
+  uint32_t n_q;
+  uint32_t n_p;
+  const uint64_t* q;
+  const uint64_t* p;
+  double log2_scale;   /* default encoding scale Delta = 2^log2_scale */
+} pvfl_params;
+
+/* Plan kinds (Sec. 3-5). */
+enum {
+  PVFL_PLAN_HYBRID = 0, /* Eq. 5 diagonals + Eq. 6 input packing + partitioning + lazy RaS (Sec. 4) */
+  PVFL_PLAN_DIAG = 1,   /* Eq. 5 alone over max(m,n) slots (Sec. 4.1) */
+  PVFL_PLAN_ROW = 2,    /* row-order (naive) method (Sec. 3.1) */
+  PVFL_PLAN_CTMAT = 3   /* [[A]] W with A sent as Eq. 5 diagonals (Alg. 3) */
+};
+
+typedef struct {
+  int32_t kind;          /* PVFL_PLAN_* */
+  int32_t m, n;          /* X is m x n (plaintext) for HYBRID/DIAG/ROW; A is m x n (encrypted) for CTMAT */
+  int32_t n_out;         /* CTMAT: columns of W (n x n_out); ignored otherwise */
+  int32_t level;         /* ciphertext level; -1 = the top level L */
+  int32_t lazy_moddown;  /* 1: one ModDown per output ciphertext (Q u P accumulation); 0: per rotation (Alg. 1 literal) */
+  int32_t ras_in_ct;     /* DIAG with m < n: 1 = rotate-and-sum inside the ciphertext, 0 = lazy RaS after decryption */
+  int32_t pack;          /* CTMAT: columns of W per plaintext (1 = Alg. 3 literal) */
+  double pt_log2_scale;  /* plaintext scale exponent; <= 0 means the context's default */
+} pvfl_plan_opts;
+
+typedef struct {
+  int32_t kind, m, n, n_out, m_pad, n_pad;
+  int32_t mprime;        /* diagonals per block (m' of Eq. 6) */
+  int32_t groups;        /* N' / n per ciphertext (input packing) */
+  int32_t row_blocks, col_blocks;
+  int32_t n_pts, pt_limbs, ct_in, ct_out, in_level, out_level, n_galois;
+  int64_t n_add, n_mult, n_rot, n_hstrot; /* Table 2 / Table 3 counts of this plan */
+  double out_log2_scale;
+} pvfl_plan_info;
+
+const char* pvfl_last_error(void);
+
+/* Context: parameters, transform tables and key-switching constants on the
+ * given HIP device.  Synchronises. */
+pvfl_status pvfl_context_create(const pvfl_params* params, int device, pvfl_ctx** out);
+void pvfl_context_destroy(pvfl_ctx* ctx);
+
+/* Secret key: uniform ternary s drawn from the Philox4x32-10 stream
+ * (seed, 0x01<<56), kept on the device transformed for every prime. */
+pvfl_status pvfl_keygen(pvfl_ctx* ctx, uint64_t seed, pvfl_sk** out);
+void pvfl_sk_destroy(pvfl_sk* sk);
+
+/* Rotation keys (hybrid key switching) for `count` Galois elements, each a
+ * power of 5 modulo 2N (RotL by i slots is 5^i, Sec. 3.1's rotation).  Key
+ * memory (count * beta * 2 * (L+1+alpha) * N doubles) is allocated by the
+ * library.  Synchronises. */
+pvfl_status pvfl_rotkeys_gen(pvfl_ctx* ctx, const pvfl_sk* sk, const uint32_t* galois, int32_t count, uint64_t seed,
+                             pvfl_rotkeys** out);
+void pvfl_rotkeys_destroy(pvfl_rotkeys* keys);
+
+/* Plans (Sec. 4 and 5): layout, partitioning, rotation list, op counts. */
+pvfl_status pvfl_plan_create(pvfl_ctx* ctx, const pvfl_plan_opts* opts, pvfl_plan** out);
+pvfl_status pvfl_plan_get_info(const pvfl_plan* plan, pvfl_plan_info* out);
+/* writes the plan's Galois elements (info.n_galois of them) */
+pvfl_status pvfl_plan_galois(const pvfl_plan* plan, uint32_t* out, int32_t cap);
+void pvfl_plan_destroy(pvfl_plan* plan);
+
+size_t pvfl_bytes_ct_in(const pvfl_plan* plan);    /* all input ciphertexts */
+size_t pvfl_bytes_ct_out(const pvfl_plan* plan);   /* all output ciphertexts */
+size_t pvfl_bytes_pt(const pvfl_plan* plan);       /* all diagonal plaintexts */
+size_t pvfl_bytes_workspace(const pvfl_plan* plan);
+
+/* The hot path.
+ * pvfl_matmul_ct_pt: out = the plan's product of the input ciphertexts and
+ *   the encoded plaintexts (Alg. 1 loop: sum_i pt_i * HstRotL(ct, i)).  ws may be
+ *   NULL (the plan then uses a workspace of its own) or a device buffer of at
+ *   least pvfl_bytes_workspace bytes.  Errors: PVFL_E_NOKEY, PVFL_E_SHAPE. */
+pvfl_status pvfl_matmul_ct_pt(const pvfl_plan* plan, const void* ct_dev, const void* pt_dev, const pvfl_rotkeys* keys,
+                              void* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Integer-level entry points (exact residues; used for bit-exact parity).
+ * m_dev: int64 coefficient vectors [count][N] on the device.
+ * pvfl_pt_import: plaintexts [count][limbs][N] with limbs = level+1 (+alpha if with_p).
+ * pvfl_encrypt_coeffs: secret-key encryption at `level`; noise and `a` drawn
+ *   from the Philox streams (seed, 0x03<<56) and (seed, 0x02<<56 | limb).
+ * pvfl_export_coeffs: evaluation-domain polys [count][limbs][N] -> canonical
+ *   uint64 coefficient residues, same layout.
+ * pvfl_decrypt_coeffs: c0 + c1 s as canonical uint64 residues [level+1][N]. */
+pvfl_status pvfl_pt_import(pvfl_ctx* ctx, int32_t level, int32_t with_p, const int64_t* m_dev, int32_t count,
+                           void* pt_dev, void* stream);
+pvfl_status pvfl_encrypt_coeffs(pvfl_ctx* ctx, const pvfl_sk* sk, int32_t level, const int64_t* m_dev, uint64_t seed,
+                                void* ct_dev, void* stream);
+pvfl_status pvfl_export_coeffs(pvfl_ctx* ctx, int32_t level, int32_t with_p, const void* poly_dev, int32_t count,
+                               uint64_t* out_dev, void* stream);
+pvfl_status pvfl_decrypt_coeffs(pvfl_ctx* ctx, const pvfl_sk* sk, int32_t level, const void* ct_dev, uint64_t* out_dev,
+                                void* stream);
+/* secret key and rotation keys as canonical uint64 coefficient residues:
+ * sk -> [L+1+alpha][N];  key k -> [beta_L][2 (b, a)][L+1+alpha][N] */
+pvfl_status pvfl_sk_export(const pvfl_sk* sk, uint64_t* out_dev, void* stream);
+pvfl_status pvfl_rotkeys_export(const pvfl_rotkeys* keys, int32_t index, uint64_t* out_dev, void* stream);
+
+/* Single operations on one ciphertext at `level` (O1-O4 of Sec. 2.2).
+ * pvfl_rotate: RotL by the Galois element (O3: automorphism, then ModUp, key
+ *   product, ModDown; hoisted = 1 gives O4's order: ModUp of c1 first, the
+ *   automorphism applied to the extended digits).
+ * pvfl_rescale: divide by q_level with rounding; out has level-1.
+ * pvfl_ct_mul_pt / pvfl_ct_add: slot-wise product / sum. */
+pvfl_status pvfl_rotate(pvfl_ctx* ctx, const pvfl_rotkeys* keys, int32_t level, const void* ct_dev, uint32_t galois,
+                        int32_t hoisted, void* out_dev, void* stream);
+pvfl_status pvfl_rescale(pvfl_ctx* ctx, int32_t level, const void* ct_dev, void* out_dev, void* stream);
+pvfl_status pvfl_ct_mul_pt(pvfl_ctx* ctx, int32_t level, const void* ct_dev, const void* pt_dev, void* out_dev,
+                           void* stream);
+pvfl_status pvfl_ct_add(pvfl_ctx* ctx, int32_t level, const void* a_dev, const void* b_dev, void* out_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PVFL_H */

@@ -1,0 +1,444 @@
+// Plans of the packed-HE matrix product and their execution.
+//
+// HYBRID (Sec. 4): Eq. 5 diagonals applied blockwise to the Eq. 6 packed
+// matrix, input partitioning when m or n exceed N' = N/2 slots, lazy
+// rotate-and-sum after decryption.  With m, n zero-padded to powers of two
+// (Sec. 3) and S = N':
+//   bm = min(m, S), bn = min(n, S), m' = max(1, bm bn / S), G = S / bn,
+//   row blocks m/S (outputs), column blocks n/S (inputs, summed),
+//   diagonal i < m' of block (b, c) at slot g bn + j holds
+//   X[b S + g m' + (j mod m'), c S + (i + j) mod bn].
+// DIAG (Sec. 4.1): Eq. 5 alone, min(m,n) diagonals over max(m,n) slots, with
+// the final rotate-and-sum either inside the ciphertext (O3) or lazy.
+// ROW (Sec. 3.1): per row, Mult, log2 n rotate-and-sum steps, indicator,
+// placement rotation, two rescales.
+// CTMAT (Alg. 3): the encrypted matrix arrives as its Eq. 5 diagonals; each
+// output is sum_i [[e_i]] * w_i with no rotation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "capi_internal.hpp"
+
+using namespace pvfl;
+
+#define HIP_TRY(expr)                                          \
+  do {                                                         \
+    hipError_t _e = (expr);                                    \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);          \
+  } while (0)
+
+static int pow2_ceil(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+static int ilog2(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+
+pvfl_plan::~pvfl_plan() {
+  if (iota_dev) hipFree(iota_dev);
+  if (own_ws) hipFree(own_ws);
+}
+
+static uint32_t galois_rotl(int i, int N) {
+  const int half = N / 2;
+  i = ((i % half) + half) % half;
+  uint64_t g = 1;
+  for (int k = 0; k < i; ++k) g = g * 5 % (2 * (uint64_t)N);
+  return (uint32_t)g;
+}
+
+extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pvfl_plan** out) {
+  if (!c || !o || !out) return fail(PVFL_E_INVALID, "null argument");
+  *out = nullptr;
+  if (o->m < 1 || o->n < 1) return fail(PVFL_E_SHAPE, "m and n must be positive");
+  std::unique_ptr<pvfl_plan> p(new pvfl_plan());
+  p->ctx = c;
+  p->opts = *o;
+  const int N = c->N, S = N / 2;
+  const int lv = o->level < 0 ? c->n_q - 1 : o->level;
+  if (lv >= c->n_q) return fail(PVFL_E_LEVEL, "level out of range");
+  p->lv = lv;
+  p->K = lv + 1 + c->alpha;
+  p->beta = (lv + 1 + c->alpha - 1) / c->alpha;
+  p->pt_scale = std::ldexp(1.0, 0) * std::pow(2.0, o->pt_log2_scale > 0 ? o->pt_log2_scale : c->log2_scale);
+  pvfl_plan_info& I = p->info;
+  std::memset(&I, 0, sizeof(I));
+  I.kind = o->kind;
+  I.m = o->m;
+  I.n = o->n;
+  I.n_out = o->n_out;
+  I.m_pad = pow2_ceil(o->m);
+  I.n_pad = pow2_ceil(o->n);
+  I.in_level = lv;
+  I.out_level = lv;
+  const double lds = c->log2_scale + std::log2(p->pt_scale);
+  I.out_log2_scale = lds;
+  const bool lazy = o->lazy_moddown != 0;
+  switch (o->kind) {
+    case PVFL_PLAN_HYBRID: {
+      const int mp = I.m_pad, np = I.n_pad;
+      I.row_blocks = std::max(1, mp / S);
+      I.col_blocks = std::max(1, np / S);
+      p->bm = std::min(mp, S);
+      p->bn = std::min(np, S);
+      I.mprime = std::max(1, (int)((int64_t)p->bm * p->bn / S));
+      I.groups = S / p->bn;
+      for (int b = 0; b < I.row_blocks; ++b)
+        for (int cb = 0; cb < I.col_blocks; ++cb)
+          for (int i = 0; i < I.mprime; ++i)
+            p->terms.push_back(Term{cb, i, (b * I.col_blocks + cb) * I.mprime + i, b});
+      I.n_pts = (int)p->terms.size();
+      I.ct_in = I.col_blocks;
+      I.ct_out = I.row_blocks;
+      for (int i = 1; i < I.mprime; ++i) p->galois.push_back(galois_rotl(i, N));
+      I.n_mult = I.n_pts;
+      I.n_add = I.n_pts - I.row_blocks;
+      I.n_rot = 0;
+      I.n_hstrot = (int64_t)I.col_blocks * (I.mprime - 1);
+      break;
+    }
+    case PVFL_PLAN_DIAG: {
+      const int mp = I.m_pad, np = I.n_pad;
+      if (mp > S || np > S) return fail(PVFL_E_SHAPE, "DIAG needs m, n <= N/2 (no partitioning)");
+      const int nd = std::min(mp, np);
+      I.mprime = nd;
+      I.groups = 1;
+      I.row_blocks = I.col_blocks = 1;
+      p->bm = mp;
+      p->bn = np;
+      for (int i = 0; i < nd; ++i) p->terms.push_back(Term{0, i, i, 0});
+      I.n_pts = nd;
+      I.ct_in = I.ct_out = 1;
+      for (int i = 1; i < nd; ++i) p->galois.push_back(galois_rotl(i, N));
+      if (mp < np && o->ras_in_ct)
+        for (int k = mp; k < np; k *= 2) {
+          p->ras_rots.push_back(k);
+          p->galois.push_back(galois_rotl(k, N));
+        }
+      I.n_mult = nd;
+      I.n_rot = (int64_t)p->ras_rots.size();
+      I.n_add = nd - 1 + I.n_rot;
+      I.n_hstrot = nd - 1;
+      break;
+    }
+    case PVFL_PLAN_ROW: {
+      const int np = I.n_pad;
+      if (np > S || o->m > S) return fail(PVFL_E_SHAPE, "ROW needs m, n <= N/2");
+      if (lv < 2) return fail(PVFL_E_LEVEL, "ROW consumes two levels (two rescales)");
+      I.mprime = 1;
+      I.row_blocks = I.col_blocks = 1;
+      I.n_pts = o->m + 1;  // one row plaintext per row, then the indicator
+      I.ct_in = I.ct_out = 1;
+      const int logn = ilog2(np);
+      for (int k = 0; k < logn; ++k) p->ras_rots.push_back(1 << k);
+      for (int k : p->ras_rots) p->galois.push_back(galois_rotl(k, N));
+      for (int r = 1; r < o->m; ++r) p->galois.push_back(galois_rotl(-r, N));
+      I.n_mult = 2 * (int64_t)o->m;
+      I.n_rot = (int64_t)o->m * logn + o->m - 1;
+      I.n_add = I.n_rot;
+      I.n_hstrot = 0;
+      I.out_level = lv - 2;
+      I.out_log2_scale = lds - std::log2((double)c->primes[lv]);
+      break;
+    }
+    case PVFL_PLAN_CTMAT: {
+      const int mp = I.m_pad, np = I.n_pad;
+      const int width = std::max(mp, np);
+      const int pack = std::max(1, o->pack);
+      if (o->n_out < 1) return fail(PVFL_E_SHAPE, "CTMAT needs n_out >= 1");
+      if ((int64_t)width * pack > S) return fail(PVFL_E_SHAPE, "CTMAT needs pack * max(m,n) <= N/2");
+      I.mprime = std::min(mp, np);
+      I.groups = pack;
+      I.row_blocks = I.col_blocks = 1;
+      I.ct_in = I.mprime;
+      I.ct_out = (o->n_out + pack - 1) / pack;
+      I.n_pts = I.ct_in * I.ct_out;
+      p->bm = mp;
+      p->bn = np;
+      I.n_mult = I.n_pts;
+      I.n_add = I.n_pts - I.ct_out;
+      break;
+    }
+    default:
+      return fail(PVFL_E_PLAN, "unknown plan kind");
+  }
+  std::sort(p->galois.begin(), p->galois.end());
+  p->galois.erase(std::unique(p->galois.begin(), p->galois.end()), p->galois.end());
+  I.n_galois = (int)p->galois.size();
+  I.pt_limbs = (lazy && (o->kind == PVFL_PLAN_HYBRID || o->kind == PVFL_PLAN_DIAG)) ? p->K : lv + 1;
+  // fused-kernel chunking: aim for >= 4096 workgroups per launch
+  const int mprime = std::max(1, I.mprime);
+  const int per_chunk = (N / 256) * p->K;
+  int target = std::max(1, std::min(64, 4096 / std::max(1, per_chunk)));
+  p->chunk = std::max(1, (mprime + target - 1) / target);
+  p->nchunk = (mprime + p->chunk - 1) / p->chunk;
+  std::vector<int> iota(mprime);
+  for (int i = 0; i < mprime; ++i) iota[i] = i;
+  if (hipMalloc((void**)&p->iota_dev, sizeof(int) * mprime) != hipSuccess) return fail(PVFL_E_NOMEM, "plan tables");
+  HIP_TRY(hipMemcpy(p->iota_dev, iota.data(), sizeof(int) * mprime, hipMemcpyHostToDevice));
+  *out = p.release();
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_plan_get_info(const pvfl_plan* p, pvfl_plan_info* out) {
+  if (!p || !out) return fail(PVFL_E_INVALID, "null argument");
+  *out = p->info;
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_plan_galois(const pvfl_plan* p, uint32_t* out, int32_t cap) {
+  if (!p || (!out && cap > 0)) return fail(PVFL_E_INVALID, "null argument");
+  if (cap < (int)p->galois.size()) return fail(PVFL_E_INVALID, "output too small");
+  std::copy(p->galois.begin(), p->galois.end(), out);
+  return PVFL_OK;
+}
+
+extern "C" void pvfl_plan_destroy(pvfl_plan* p) { delete p; }
+
+extern "C" size_t pvfl_bytes_ct_in(const pvfl_plan* p) {
+  return p ? sizeof(double) * 2 * (size_t)(p->lv + 1) * p->ctx->N * p->info.ct_in : 0;
+}
+extern "C" size_t pvfl_bytes_ct_out(const pvfl_plan* p) {
+  return p ? sizeof(double) * 2 * (size_t)(p->info.out_level + 1) * p->ctx->N * p->info.ct_out : 0;
+}
+extern "C" size_t pvfl_bytes_pt(const pvfl_plan* p) {
+  return p ? sizeof(double) * (size_t)p->info.pt_limbs * p->ctx->N * p->info.n_pts : 0;
+}
+
+// workspace layout (doubles), per plan kind
+static size_t ws_doubles(const pvfl_plan* p) {
+  const pvfl_ctx* c = p->ctx;
+  const size_t N = c->N, Q = (size_t)(p->lv + 1) * N, KN = (size_t)p->K * N;
+  const size_t digits = (size_t)p->beta * KN;
+  const size_t ydown = 2 * (size_t)c->alpha * N;
+  switch (p->opts.kind) {
+    case PVFL_PLAN_HYBRID:
+    case PVFL_PLAN_DIAG:
+      if (p->opts.lazy_moddown)
+        return digits + Q + 2 * Q + (size_t)p->info.col_blocks * p->nchunk * 2 * KN + 2 * KN + ydown + 4 * Q;
+      return digits + Q + 2 * KN + ydown + 2 * Q + 4 * Q;
+    case PVFL_PLAN_ROW:
+      return 8 * Q;
+    case PVFL_PLAN_CTMAT:
+      return 0;
+  }
+  return 0;
+}
+extern "C" size_t pvfl_bytes_workspace(const pvfl_plan* p) { return p ? sizeof(double) * std::max<size_t>(ws_doubles(p), 1) : 0; }
+
+static pvfl_status get_ws(const pvfl_plan* p, void* ws, size_t ws_bytes, double** out) {
+  const size_t need = pvfl_bytes_workspace(p);
+  if (ws) {
+    if (ws_bytes < need) return fail(PVFL_E_SHAPE, "workspace too small");
+    *out = (double*)ws;
+    return PVFL_OK;
+  }
+  if (p->own_ws_bytes < need) {
+    if (p->own_ws) hipFree(p->own_ws);
+    p->own_ws = nullptr;
+    p->own_ws_bytes = 0;
+    if (hipMalloc((void**)&p->own_ws, need) != hipSuccess) return fail(PVFL_E_NOMEM, "workspace allocation");
+    p->own_ws_bytes = need;
+  }
+  *out = p->own_ws;
+  return PVFL_OK;
+}
+
+static pvfl_status check_keys(const pvfl_plan* p, const pvfl_rotkeys* keys) {
+  if (p->galois.empty()) return PVFL_OK;
+  if (!keys) return fail(PVFL_E_NOKEY, "plan needs rotation keys");
+  if (keys->ctx != p->ctx) return fail(PVFL_E_INVALID, "keys belong to another context");
+  for (uint32_t g : p->galois)
+    if (keys->slot_of_rot[p->ctx->log5[g]] < 0)
+      return fail(PVFL_E_NOKEY, "missing rotation key for Galois element " + std::to_string(g));
+  return PVFL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// diagonal products (HYBRID, DIAG)
+// ---------------------------------------------------------------------------
+static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const double* pts, const pvfl_rotkeys* keys,
+                                 double* out, double* ws, void* stream) {
+  pvfl_ctx* c = p->ctx;
+  const int N = c->N, lv = p->lv, K = p->K;
+  const size_t Q = (size_t)(lv + 1) * N, KN = (size_t)K * N;
+  const KsLevel& kl = c->ks_host[lv];
+  double* digits = ws;
+  double* yup = digits + (size_t)p->beta * KN;
+  double* pc = yup + Q;
+  double* part = pc + 2 * Q;
+  double* acc = part + (size_t)p->info.col_blocks * p->nchunk * 2 * KN;
+  double* ydown = acc + 2 * KN;
+  LaunchCtx L = launch_ctx(c, stream);
+  const int mprime = p->info.mprime;
+  DiagArgs a{};
+  a.N = N;
+  a.K = K;
+  a.lv = lv;
+  a.beta = p->beta;
+  a.mprime = mprime;
+  a.chunk = p->chunk;
+  a.mods = c->tabs.mods;
+  const LimbMap lp = qp_map(c, lv, true);
+  for (int r = 0; r < K; ++r) {
+    a.limb_prime[r] = lp.idx[r];
+    a.key_limb[r] = lp.idx[r];
+  }
+  a.pt_index = p->iota_dev;
+  a.rot = p->iota_dev;
+  a.digits = digits;
+  a.pc = pc;
+  if (keys) {
+    a.keys = keys->keys;
+    a.key_limbs = keys->key_limbs;
+    a.key_stride = keys->key_stride;
+    a.slot_of_rot = keys->slot_of_rot_dev;
+  }
+  for (int b = 0; b < p->info.row_blocks; ++b) {
+    int z = 0;
+    for (int cb = 0; cb < p->info.col_blocks; ++cb) {
+      const double* ct = ct_in + (size_t)cb * 2 * Q;
+      if (mprime > 1) HIP_TRY(launch_modup(L, ct + Q, lv, c->ks_dev + lv, kl.n_tasks, yup, digits));
+      HIP_TRY(launch_scale_by_p(L, ct, lv, N, c->pmod_dev, pc));
+      a.pt = pts + (size_t)(b * p->info.col_blocks + cb) * mprime * KN;
+      a.part = part + (size_t)z * 2 * KN;
+      HIP_TRY(launch_diag_lazy(L, a, p->nchunk));
+      z += p->nchunk;
+    }
+    HIP_TRY(launch_sum_partials(L, part, z, K, N, lp, acc));
+    HIP_TRY(launch_moddown(L, acc, 2, lv, c->alpha, c->ks_dev + lv, ydown, out + (size_t)b * 2 * Q));
+  }
+  return PVFL_OK;
+}
+
+static pvfl_status run_diag_eager(const pvfl_plan* p, const double* ct_in, const double* pts, const pvfl_rotkeys* keys,
+                                  double* out, double* ws, void* stream) {
+  pvfl_ctx* c = p->ctx;
+  const int N = c->N, lv = p->lv, K = p->K;
+  const size_t Q = (size_t)(lv + 1) * N, KN = (size_t)K * N;
+  const KsLevel& kl = c->ks_host[lv];
+  double* digits = ws;
+  double* yup = digits + (size_t)p->beta * KN;
+  double* u = yup + Q;
+  double* ydown = u + 2 * KN;
+  double* v = ydown + 2 * (size_t)c->alpha * N;
+  LaunchCtx L = launch_ctx(c, stream);
+  const int mprime = p->info.mprime;
+  for (int b = 0; b < p->info.row_blocks; ++b) {
+    double* acc = out + (size_t)b * 2 * Q;
+    HIP_TRY(launch_fill_zero(L, acc, 2 * Q));
+    for (int cb = 0; cb < p->info.col_blocks; ++cb) {
+      const double* ct = ct_in + (size_t)cb * 2 * Q;
+      if (mprime > 1) HIP_TRY(launch_modup(L, ct + Q, lv, c->ks_dev + lv, kl.n_tasks, yup, digits));
+      for (int i = 0; i < mprime; ++i) {
+        const double* pt = pts + ((size_t)(b * p->info.col_blocks + cb) * mprime + i) * Q;
+        if (i == 0) {
+          HIP_TRY(launch_eager_term(L, ct, ct + Q, nullptr, 0, pt, lv, N, acc));
+        } else {
+          pvfl_status st = keyswitch_digits(c, keys, lv, digits, i, i, u, ydown, v, stream);
+          if (st != PVFL_OK) return st;
+          HIP_TRY(launch_eager_term(L, ct, nullptr, v, i, pt, lv, N, acc));
+        }
+      }
+    }
+  }
+  return PVFL_OK;
+}
+
+// in-ciphertext rotate-and-sum (DIAG, m < n): ct += RotL(ct, k) for each k
+static pvfl_status run_ras_in_ct(const pvfl_plan* p, const pvfl_rotkeys* keys, double* ct, double* tmp, void* stream) {
+  pvfl_ctx* c = p->ctx;
+  const size_t Q = (size_t)(p->lv + 1) * c->N;
+  for (int k : p->ras_rots) {
+    pvfl_status st = pvfl_rotate(c, keys, p->lv, ct, galois_rotl(k, c->N), 0, tmp, stream);
+    if (st != PVFL_OK) return st;
+    HIP_TRY(launch_ct_add(launch_ctx(c, stream), ct, tmp, p->lv, c->N, ct));
+  }
+  (void)Q;
+  return PVFL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ROW (Sec. 3.1)
+// ---------------------------------------------------------------------------
+static pvfl_status run_row(const pvfl_plan* p, const double* ct, const double* pts, const pvfl_rotkeys* keys,
+                           double* out, double* ws, void* stream) {
+  pvfl_ctx* c = p->ctx;
+  const int N = c->N, lv = p->lv;
+  const size_t Q2 = (size_t)(lv + 1) * N, Q1 = (size_t)lv * N, Q0 = (size_t)(lv - 1) * N;
+  double* t2 = ws;              // product at lv
+  double* t1 = t2 + 2 * Q2;     // after the first rescale (lv - 1)
+  double* r1 = t1 + 2 * Q2;     // rotation temporary
+  double* t0 = r1 + 2 * Q2;     // after the indicator rescale (lv - 2)
+  LaunchCtx L = launch_ctx(c, stream);
+  const int m = p->info.m;
+  const double* ind = pts + (size_t)m * Q2;  // indicator plaintext (level lv - 1 limbs used)
+  HIP_TRY(launch_fill_zero(L, out, 2 * Q0));
+  pvfl_status st;
+  for (int r = 0; r < m; ++r) {
+    HIP_TRY(launch_ct_mul_pt(L, ct, pts + (size_t)r * Q2, lv, N, t2));
+    HIP_TRY(launch_rescale(L, t2, 2, lv, c->rescale[lv], t1));
+    for (int k : p->ras_rots) {
+      if ((st = pvfl_rotate(c, keys, lv - 1, t1, galois_rotl(k, N), 0, r1, stream)) != PVFL_OK) return st;
+      HIP_TRY(launch_ct_add(L, t1, r1, lv - 1, N, t1));
+    }
+    // the indicator plaintext is stored with lv+1 limbs; its first lv are used here
+    HIP_TRY(launch_ct_mul_pt(L, t1, ind, lv - 1, N, r1));
+    HIP_TRY(launch_rescale(L, r1, 2, lv - 1, c->rescale[lv - 1], t0));
+    if (r > 0) {
+      if ((st = pvfl_rotate(c, keys, lv - 2, t0, galois_rotl(-r, N), 0, r1, stream)) != PVFL_OK) return st;
+      HIP_TRY(launch_ct_add(L, out, r1, lv - 2, N, out));
+    } else {
+      HIP_TRY(launch_ct_add(L, out, t0, lv - 2, N, out));
+    }
+  }
+  (void)Q1;
+  return PVFL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// entry point
+// ---------------------------------------------------------------------------
+extern "C" pvfl_status pvfl_matmul_ct_pt(const pvfl_plan* p, const void* ct_v, const void* pt_v,
+                                         const pvfl_rotkeys* keys, void* out_v, void* ws_v, size_t ws_bytes,
+                                         void* stream) {
+  if (!p || !ct_v || !pt_v || !out_v) return fail(PVFL_E_INVALID, "null argument");
+  pvfl_status st = check_keys(p, keys);
+  if (st != PVFL_OK) return st;
+  double* ws = nullptr;
+  if ((st = get_ws(p, ws_v, ws_bytes, &ws)) != PVFL_OK) return st;
+  const double* ct = (const double*)ct_v;
+  const double* pt = (const double*)pt_v;
+  double* out = (double*)out_v;
+  switch (p->opts.kind) {
+    case PVFL_PLAN_HYBRID:
+    case PVFL_PLAN_DIAG: {
+      st = p->opts.lazy_moddown ? run_diag_lazy(p, ct, pt, keys, out, ws, stream)
+                                : run_diag_eager(p, ct, pt, keys, out, ws, stream);
+      if (st != PVFL_OK) return st;
+      if (p->opts.kind == PVFL_PLAN_DIAG && !p->ras_rots.empty()) {
+        const size_t Q = (size_t)(p->lv + 1) * p->ctx->N;
+        double* tmp = ws + ws_doubles(p) - 4 * Q;
+        return run_ras_in_ct(p, keys, out, tmp, stream);
+      }
+      return PVFL_OK;
+    }
+    case PVFL_PLAN_ROW:
+      return run_row(p, ct, pt, keys, out, ws, stream);
+    case PVFL_PLAN_CTMAT: {
+      LaunchCtx L = launch_ctx(p->ctx, stream);
+      HIP_TRY(launch_ctmat(L, ct, pt, p->info.ct_in, p->info.ct_out, p->lv, p->ctx->N, out));
+      return PVFL_OK;
+    }
+  }
+  return fail(PVFL_E_PLAN, "unknown plan kind");
+}

@@ -1,0 +1,250 @@
+"""Python binding of the C ABI declared in include/pvfl.h.
+
+Argument marshalling only: torch tensors provide device memory (their
+data_ptr()) and the current HIP stream; every step of the computation runs in
+the HIP library libpvfl.so.  Importing works without a GPU; any call that
+needs the library raises if libpvfl.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpvfl.so")
+
+PLAN_HYBRID, PLAN_DIAG, PLAN_ROW, PLAN_CTMAT = 0, 1, 2, 3
+
+_STATUS = {0: "OK", -1: "PVFL_E_INVALID", -2: "PVFL_E_SHAPE", -3: "PVFL_E_LEVEL", -4: "PVFL_E_NOKEY",
+           -5: "PVFL_E_NOMEM", -6: "PVFL_E_DEVICE", -7: "PVFL_E_PLAN"}
+
+
+class PvflError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("n_p", ctypes.c_uint32),
+                ("q", ctypes.POINTER(ctypes.c_uint64)), ("p", ctypes.POINTER(ctypes.c_uint64)),
+                ("log2_scale", ctypes.c_double)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("level", ctypes.c_int32), ("lazy_moddown", ctypes.c_int32), ("ras_in_ct", ctypes.c_int32),
+                ("pack", ctypes.c_int32), ("pt_log2_scale", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("kind", "m", "n", "n_out", "m_pad", "n_pad", "mprime", "groups",
+                                              "row_blocks", "col_blocks", "n_pts", "pt_limbs", "ct_in", "ct_out",
+                                              "in_level", "out_level", "n_galois")] + \
+               [(n, ctypes.c_int64) for n in ("n_add", "n_mult", "n_rot", "n_hstrot")] + \
+               [("out_log2_scale", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        # torch bundles its own HIP runtime with the same soname as the system
+        # one; loading torch first makes libpvfl bind to that single runtime,
+        # so torch tensors and library calls share one device context.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        L.pvfl_last_error.restype = ctypes.c_char_p
+        i32, u64, u32, sz = ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_size_t
+        sig = {
+            "pvfl_context_create": [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(_VP)],
+            "pvfl_keygen": [_VP, u64, ctypes.POINTER(_VP)],
+            "pvfl_rotkeys_gen": [_VP, _VP, ctypes.POINTER(u32), i32, u64, ctypes.POINTER(_VP)],
+            "pvfl_plan_create": [_VP, ctypes.POINTER(PlanOpts), ctypes.POINTER(_VP)],
+            "pvfl_plan_get_info": [_VP, ctypes.POINTER(PlanInfo)],
+            "pvfl_plan_galois": [_VP, ctypes.POINTER(u32), i32],
+            "pvfl_matmul_ct_pt": [_VP, _VP, _VP, _VP, _VP, _VP, sz, _VP],
+            "pvfl_pt_import": [_VP, i32, i32, _VP, i32, _VP, _VP],
+            "pvfl_encrypt_coeffs": [_VP, _VP, i32, _VP, u64, _VP, _VP],
+            "pvfl_export_coeffs": [_VP, i32, i32, _VP, i32, _VP, _VP],
+            "pvfl_decrypt_coeffs": [_VP, _VP, i32, _VP, _VP, _VP],
+            "pvfl_sk_export": [_VP, _VP, _VP],
+            "pvfl_rotkeys_export": [_VP, i32, _VP, _VP],
+            "pvfl_rotate": [_VP, _VP, i32, _VP, u32, i32, _VP, _VP],
+            "pvfl_rescale": [_VP, i32, _VP, _VP, _VP],
+            "pvfl_ct_mul_pt": [_VP, i32, _VP, _VP, _VP, _VP],
+            "pvfl_ct_add": [_VP, i32, _VP, _VP, _VP, _VP],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        for name in ("pvfl_bytes_ct_in", "pvfl_bytes_ct_out", "pvfl_bytes_pt", "pvfl_bytes_workspace"):
+            f = getattr(L, name)
+            f.argtypes = [_VP]
+            f.restype = sz
+        for name in ("pvfl_context_destroy", "pvfl_sk_destroy", "pvfl_rotkeys_destroy", "pvfl_plan_destroy"):
+            f = getattr(L, name)
+            f.argtypes = [_VP]
+            f.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise PvflError(status, lib().pvfl_last_error().decode())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class _Handle:
+    _destroy = ""
+
+    def __init__(self, h, keep=()):
+        self.h = h
+        self._keep = keep
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            getattr(lib(), self._destroy)(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context(_Handle):
+    _destroy = "pvfl_context_destroy"
+
+    def __init__(self, logN: int, q, p, log2_scale: float, device: int = 0):
+        self.logN, self.N = logN, 1 << logN
+        self.q, self.p = [int(x) for x in q], [int(x) for x in p]
+        self.log2_scale = log2_scale
+        qa = (ctypes.c_uint64 * len(self.q))(*self.q)
+        pa = (ctypes.c_uint64 * len(self.p))(*self.p)
+        prm = Params(logN, len(self.q), len(self.p), qa, pa, log2_scale)
+        h = _VP()
+        _check(lib().pvfl_context_create(ctypes.byref(prm), device, ctypes.byref(h)))
+        super().__init__(h)
+
+    @staticmethod
+    def from_dict(d: dict, device: int = 0) -> "Context":
+        return Context(int(d["logN"]), d["q"], d["p"], float(d["log2_scale"]), device)
+
+    @property
+    def L(self) -> int:
+        return len(self.q) - 1
+
+    @property
+    def alpha(self) -> int:
+        return len(self.p)
+
+    def keygen(self, seed: int) -> "SecretKey":
+        h = _VP()
+        _check(lib().pvfl_keygen(self.h, seed, ctypes.byref(h)))
+        return SecretKey(h, keep=(self,))
+
+    def rotkeys(self, sk: "SecretKey", galois, seed: int) -> "RotKeys":
+        g = [int(x) for x in galois]
+        arr = (ctypes.c_uint32 * max(1, len(g)))(*g)
+        h = _VP()
+        _check(lib().pvfl_rotkeys_gen(self.h, sk.h, arr, len(g), seed, ctypes.byref(h)))
+        return RotKeys(h, list(g), keep=(self,))
+
+    def plan(self, kind: int, m: int, n: int, n_out: int = 0, level: int = -1, lazy: bool = True,
+             ras_in_ct: bool = False, pack: int = 1, pt_log2_scale: float = 0.0) -> "Plan":
+        o = PlanOpts(kind, m, n, n_out, level, int(lazy), int(ras_in_ct), pack, pt_log2_scale)
+        h = _VP()
+        _check(lib().pvfl_plan_create(self.h, ctypes.byref(o), ctypes.byref(h)))
+        return Plan(h, self)
+
+    # integer-level entries
+    def pt_import(self, level: int, with_p: bool, m_i64, out):
+        count = m_i64.shape[0]
+        _check(lib().pvfl_pt_import(self.h, level, int(with_p), _ptr(m_i64), count, _ptr(out), _stream()))
+
+    def encrypt_coeffs(self, sk, level: int, m_i64, seed: int, out):
+        _check(lib().pvfl_encrypt_coeffs(self.h, sk.h, level, _ptr(m_i64), seed, _ptr(out), _stream()))
+
+    def export_coeffs(self, level: int, with_p: bool, poly, count: int, out):
+        _check(lib().pvfl_export_coeffs(self.h, level, int(with_p), _ptr(poly), count, _ptr(out), _stream()))
+
+    def decrypt_coeffs(self, sk, level: int, ct, out):
+        _check(lib().pvfl_decrypt_coeffs(self.h, sk.h, level, _ptr(ct), _ptr(out), _stream()))
+
+    def rotate(self, keys, level: int, ct, galois: int, hoisted: bool, out):
+        _check(lib().pvfl_rotate(self.h, keys.h, level, _ptr(ct), galois, int(hoisted), _ptr(out), _stream()))
+
+    def rescale(self, level: int, ct, out):
+        _check(lib().pvfl_rescale(self.h, level, _ptr(ct), _ptr(out), _stream()))
+
+    def ct_mul_pt(self, level: int, ct, pt, out):
+        _check(lib().pvfl_ct_mul_pt(self.h, level, _ptr(ct), _ptr(pt), _ptr(out), _stream()))
+
+    def ct_add(self, level: int, a, b, out):
+        _check(lib().pvfl_ct_add(self.h, level, _ptr(a), _ptr(b), _ptr(out), _stream()))
+
+
+class SecretKey(_Handle):
+    _destroy = "pvfl_sk_destroy"
+
+    def export(self, out):
+        _check(lib().pvfl_sk_export(self.h, _ptr(out), _stream()))
+
+
+class RotKeys(_Handle):
+    _destroy = "pvfl_rotkeys_destroy"
+
+    def __init__(self, h, galois, keep=()):
+        super().__init__(h, keep)
+        self.galois = galois
+
+    def export(self, index: int, out):
+        _check(lib().pvfl_rotkeys_export(self.h, index, _ptr(out), _stream()))
+
+
+class Plan(_Handle):
+    _destroy = "pvfl_plan_destroy"
+
+    def __init__(self, h, ctx: Context):
+        super().__init__(h, keep=(ctx,))
+        self.ctx = ctx
+        info = PlanInfo()
+        _check(lib().pvfl_plan_get_info(self.h, ctypes.byref(info)))
+        self.info = info.as_dict()
+
+    def galois(self) -> list:
+        n = self.info["n_galois"]
+        arr = (ctypes.c_uint32 * max(1, n))()
+        _check(lib().pvfl_plan_galois(self.h, arr, n))
+        return [int(arr[i]) for i in range(n)]
+
+    def bytes(self, what: str) -> int:
+        return int(getattr(lib(), "pvfl_bytes_" + what)(self.h))
+
+    def matmul(self, ct, pt, keys, out, ws=None):
+        ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+        _check(lib().pvfl_matmul_ct_pt(self.h, _ptr(ct), _ptr(pt), keys.h if keys is not None else None, _ptr(out),
+                                       _ptr(ws), ws_bytes, _stream()))
