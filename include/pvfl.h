@@ -140,6 +140,26 @@ size_t pvfl_bytes_workspace(const pvfl_plan* plan);
 pvfl_status pvfl_matmul_ct_pt(const pvfl_plan* plan, const void* ct_dev, const void* pt_dev, const pvfl_rotkeys* keys,
                               void* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Real-valued path (canonical-embedding encoding, Sec. 2.2).
+ * pvfl_encode_pt: pack the plaintext matrix into the plan's diagonal
+ *   plaintexts (Eq. 5 / Eq. 6 layout; for CTMAT the matrix is W, n x n_out)
+ *   and encode them at the plan's plaintext scale.  X_dev is row-major with
+ *   row stride ld (elements).  Every slot value times the scale must stay
+ *   below 2^50 in magnitude.  pt_dev holds pvfl_bytes_pt bytes.
+ * pvfl_encrypt: the key owner's side: build the plan's input ciphertexts from
+ *   v_dev (the vector y, replicated with period n over the slots, Sec. 4.1;
+ *   for CTMAT the m x n matrix A as its Eq. 5 diagonals, row stride ld) at the
+ *   context scale, secret-key encrypted; ciphertext k uses seed + k.
+ * pvfl_decrypt_decode: decrypt the plan's output ciphertexts, lift by CRT,
+ *   decode, and apply the lazy rotate-and-sum of Sec. 4.3: y_dev receives m
+ *   values (CTMAT: the m x n_out product, row-major).  Uses the context's
+ *   scratch memory: calls on one context must be ordered on one stream. */
+pvfl_status pvfl_encode_pt(const pvfl_plan* plan, const double* X_dev, int64_t ld, void* pt_dev, void* stream);
+pvfl_status pvfl_encrypt(const pvfl_plan* plan, const pvfl_sk* sk, const double* v_dev, int64_t ld, uint64_t seed,
+                         void* ct_dev, void* stream);
+pvfl_status pvfl_decrypt_decode(const pvfl_plan* plan, const pvfl_sk* sk, const void* ct_dev, double* y_dev,
+                                void* stream);
+
 /* Integer-level entry points (exact residues; used for bit-exact parity).
  * m_dev: int64 coefficient vectors [count][N] on the device.
  * pvfl_pt_import: plaintexts [count][limbs][N] with limbs = level+1 (+alpha if with_p).

@@ -94,6 +94,8 @@ static int bit_reverse(int x, int bits) {
 // context
 // ---------------------------------------------------------------------------
 pvfl_ctx::~pvfl_ctx() {
+  if (enc_tabs && enc_tabs_free) enc_tabs_free(enc_tabs);
+  if (scratch) hipFree(scratch);
   for (void* p : dev_allocs) hipFree(p);
 }
 

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -34,6 +36,7 @@ struct pvfl_ctx {
   size_t scratch_bytes = 0;
   // encoder tables (slot <-> FFT index, twiddles), created on first use
   void* enc_tabs = nullptr;
+  void (*enc_tabs_free)(void*) = nullptr;
   ~pvfl_ctx();
 };
 

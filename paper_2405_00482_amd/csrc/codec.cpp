@@ -1,0 +1,158 @@
+// Host entries of the real-valued path: plaintext packing/encoding, encryption
+// of the encrypted operand, decryption + decoding + lazy rotate-and-sum.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "capi_internal.hpp"
+#include "encode.hpp"
+
+using namespace pvfl;
+
+#define HIP_TRY(expr)                                          \
+  do {                                                         \
+    hipError_t _e = (expr);                                    \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);          \
+  } while (0)
+
+namespace {
+struct EncHost {
+  EncTabs et{};
+  CrtTabs crt{};
+  std::vector<void*> allocs;
+  ~EncHost() {
+    for (void* p : allocs) hipFree(p);
+  }
+};
+
+pvfl_status upload(EncHost* h, const void* src, size_t bytes, void** out) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(PVFL_E_NOMEM, "encoder table allocation");
+  h->allocs.push_back(p);
+  if (hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return fail(PVFL_E_DEVICE, "table upload");
+  *out = p;
+  return PVFL_OK;
+}
+
+pvfl_status enc_tables(pvfl_ctx* c, EncHost** out) {
+  if (c->enc_tabs) {
+    *out = (EncHost*)c->enc_tabs;
+    return PVFL_OK;
+  }
+  std::unique_ptr<EncHost> h(new EncHost());
+  const int N = c->N, M = N / 2;
+  std::vector<uint32_t> slot2f(M);
+  uint64_t e = 1;
+  for (int j = 0; j < M; ++j) {
+    slot2f[j] = (uint32_t)((e - 1) / 4);
+    e = e * 5 % (2 * (uint64_t)N);
+  }
+  const long double PI = 3.141592653589793238462643383279502884L;
+  std::vector<double2> tw(M / 2), twist(M);
+  for (int t = 0; t < M / 2; ++t) {
+    const long double ang = -2.0L * PI * (long double)t / (long double)M;
+    tw[t] = make_double2((double)std::cos(ang), (double)std::sin(ang));
+  }
+  for (int k = 0; k < M; ++k) {
+    const long double ang = PI * (long double)k / (long double)N;
+    twist[k] = make_double2((double)std::cos(ang), (double)std::sin(ang));
+  }
+  std::vector<double> ginv(kMaxLimbs * kMaxLimbs, 0.0);
+  for (int i = 0; i < c->n_q; ++i)
+    for (int j = 0; j < i; ++j) ginv[j * kMaxLimbs + i] = centred(invm(c->primes[j] % c->primes[i], c->primes[i]), c->primes[i]);
+  void *d_s2f, *d_tw, *d_twist, *d_g;
+  pvfl_status st;
+  if ((st = upload(h.get(), slot2f.data(), sizeof(uint32_t) * M, &d_s2f)) != PVFL_OK) return st;
+  if ((st = upload(h.get(), tw.data(), sizeof(double2) * (M / 2), &d_tw)) != PVFL_OK) return st;
+  if ((st = upload(h.get(), twist.data(), sizeof(double2) * M, &d_twist)) != PVFL_OK) return st;
+  if ((st = upload(h.get(), ginv.data(), sizeof(double) * ginv.size(), &d_g)) != PVFL_OK) return st;
+  h->et = EncTabs{(const uint32_t*)d_s2f, (const double2*)d_tw, (const double2*)d_twist};
+  h->crt = CrtTabs{c->tabs.mods, (const double*)d_g};
+  c->enc_tabs = h.release();
+  c->enc_tabs_free = [](void* p) { delete (EncHost*)p; };
+  *out = (EncHost*)c->enc_tabs;
+  return PVFL_OK;
+}
+
+EncodeArgs plan_geometry(const pvfl_plan* p, const double* X, int64_t ld) {
+  EncodeArgs a{};
+  const pvfl_plan_info& I = p->info;
+  a.kind = I.kind;
+  a.m = I.m;
+  a.n = I.n;
+  a.ld = (int)ld;
+  a.X = X;
+  a.slots = p->ctx->N / 2;
+  a.mprime = std::max(1, I.mprime);
+  a.col_blocks = I.col_blocks;
+  a.pack = std::max(1, p->opts.pack);
+  a.n_out = I.n_out;
+  a.n_out_cts = I.ct_out;
+  switch (I.kind) {
+    case PVFL_PLAN_HYBRID: a.bm = p->bm; a.bn = p->bn; break;
+    case PVFL_PLAN_DIAG:
+    case PVFL_PLAN_CTMAT: a.bm = I.m_pad; a.bn = I.n_pad; a.width = std::max(I.m_pad, I.n_pad); break;
+    case PVFL_PLAN_ROW: a.bm = I.m_pad; a.bn = I.n_pad; break;
+  }
+  return a;
+}
+}  // namespace
+
+extern "C" pvfl_status pvfl_encode_pt(const pvfl_plan* p, const double* X, int64_t ld, void* pt, void* stream) {
+  if (!p || !X || !pt) return fail(PVFL_E_INVALID, "null argument");
+  pvfl_ctx* c = p->ctx;
+  const int need_ld = p->info.kind == PVFL_PLAN_CTMAT ? p->info.n_out : p->info.n;
+  if (ld < need_ld) return fail(PVFL_E_SHAPE, "leading dimension smaller than the row length");
+  EncHost* h;
+  pvfl_status st = enc_tables(c, &h);
+  if (st != PVFL_OK) return st;
+  EncodeArgs a = plan_geometry(p, X, ld);
+  a.scale = p->pt_scale;
+  if (p->info.kind == PVFL_PLAN_ROW) a.ind_scale = (double)c->primes[p->lv - 1];
+  LimbMap map = qp_map(c, p->lv, p->info.pt_limbs > p->lv + 1);
+  HIP_TRY(launch_encode_pt(launch_ctx(c, stream), a, h->et, map, p->info.n_pts, (double*)pt));
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_encrypt(const pvfl_plan* p, const pvfl_sk* sk, const double* v, int64_t ld, uint64_t seed,
+                                    void* ct, void* stream) {
+  if (!p || !sk || !v || !ct) return fail(PVFL_E_INVALID, "null argument");
+  pvfl_ctx* c = p->ctx;
+  if (p->info.kind == PVFL_PLAN_CTMAT && ld < p->info.n) return fail(PVFL_E_SHAPE, "leading dimension too small");
+  EncHost* h;
+  pvfl_status st = enc_tables(c, &h);
+  if (st != PVFL_OK) return st;
+  const int nct = p->info.ct_in, N = c->N, lv = p->lv;
+  double* scratch;
+  if ((st = ctx_scratch(c, sizeof(int64_t) * (size_t)nct * N, &scratch)) != PVFL_OK) return st;
+  int64_t* msg = (int64_t*)scratch;
+  EncodeArgs a = plan_geometry(p, v, ld);
+  a.scale = std::pow(2.0, c->log2_scale);
+  LaunchCtx L = launch_ctx(c, stream);
+  HIP_TRY(launch_encode_ct(L, a, h->et, nct, msg));
+  for (int k = 0; k < nct; ++k)
+    HIP_TRY(launch_encrypt(L, msg + (size_t)k * N, sk->s, seed + (uint64_t)k, lv, (double*)ct + (size_t)k * 2 * (lv + 1) * N));
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_decrypt_decode(const pvfl_plan* p, const pvfl_sk* sk, const void* ct, double* y,
+                                           void* stream) {
+  if (!p || !sk || !ct || !y) return fail(PVFL_E_INVALID, "null argument");
+  pvfl_ctx* c = p->ctx;
+  EncHost* h;
+  pvfl_status st = enc_tables(c, &h);
+  if (st != PVFL_OK) return st;
+  const int nct = p->info.ct_out, N = c->N, lv = p->info.out_level;
+  double* scratch;
+  const size_t res_n = (size_t)nct * (lv + 1) * N, z_n = (size_t)nct * (N / 2);
+  if ((st = ctx_scratch(c, sizeof(double) * (res_n + z_n), &scratch)) != PVFL_OK) return st;
+  LaunchCtx L = launch_ctx(c, stream);
+  HIP_TRY(launch_decrypt_f64(L, (const double*)ct, nct, sk->s, lv, scratch));
+  HIP_TRY(launch_decode(L, scratch, nct, lv, h->crt, h->et, std::pow(2.0, -p->info.out_log2_scale), scratch + res_n));
+  EncodeArgs a = plan_geometry(p, nullptr, 0);
+  const int count = p->info.kind == PVFL_PLAN_CTMAT ? p->info.m * p->info.n_out : p->info.m;
+  HIP_TRY(launch_readout(L, scratch + res_n, a, p->opts.ras_in_ct, count, y));
+  return PVFL_OK;
+}

@@ -1,0 +1,321 @@
+// Canonical-embedding encode/decode (FP64, gfx950) and the plaintext packing
+// of the plans.
+//
+// Slots z_j (j < N/2) are the values at zeta^(5^j), zeta = exp(i pi / N).  With
+// e_j = 5^j mod 2N = 4 f_j + 1 and w_k = m_k + i m_(k+N/2) (k < N/2):
+//     z_j = sum_k (w_k zeta^k) W^(-k f_j),   W = exp(-2 pi i / (N/2)),
+// a length-N/2 DFT of the twisted w, read at index f_j.  Encoding inverts it:
+// place scale*z_j at f_j, forward DFT / (N/2), untwist by zeta^-k, round the
+// real and imaginary parts half away from zero to m_k and m_(k+N/2).
+// The complex transform runs in LDS (N/2 complex doubles = 8N bytes) as a
+// radix-2 decimation-in-frequency FFT (natural order in, bit-reversed out).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "encode.hpp"
+#include "ntt_core.hpp"
+
+namespace pvfl {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+__device__ __forceinline__ double round_half_away(double x) {
+  const double r = __builtin_trunc(x + (x >= 0.0 ? 0.5 : -0.5));
+  return r;
+}
+
+// In-place DIF FFT over M = N/2 points in LDS, sign -1 (conj = false) or +1.
+template <int LOGN>
+__device__ __forceinline__ void fft_dif_lds(double2* a, const double2* __restrict__ tw, bool conj) {
+  constexpr int LOGM = LOGN - 1, M = 1 << LOGM;
+  constexpr int T = NttShape<LOGN>::T;
+  constexpr int BF = M / 2 / T;  // 4
+  const int tid = threadIdx.x;
+#pragma unroll 1
+  for (int s = 0; s < LOGM; ++s) {
+    const int lhalf = LOGM - 1 - s;   // log2 of half the current length
+    const int half = 1 << lhalf;
+#pragma unroll
+    for (int r = 0; r < BF; ++r) {
+      const int b = tid + r * T;
+      const int blk = b >> lhalf, j = b & (half - 1);
+      const int i0 = (blk << (lhalf + 1)) + j, i1 = i0 + half;
+      double2 w = tw[j << s];  // W_len^j = W_M^(j M/len)
+      if (conj) w = cconj(w);
+      const double2 u = a[i0], v = a[i1];
+      a[i0] = make_double2(u.x + v.x, u.y + v.y);
+      a[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int brev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
+
+// value of slot s of plaintext k for the plan (0 outside the matrix)
+__device__ __forceinline__ double pt_slot_value(const EncodeArgs& a, int k, int s) {
+  switch (a.kind) {
+    case 0: {  // HYBRID: block (b, c), diagonal i; slot s = g bn + j
+      const int per = a.col_blocks * a.mprime;
+      const int b = k / per, c = (k / a.mprime) % a.col_blocks, i = k % a.mprime;
+      const int g = s / a.bn, j = s % a.bn;
+      const int rr = g * a.mprime + (j % a.mprime);
+      if (rr >= a.bm) return 0.0;
+      const int row = b * a.bm + rr, col = c * a.bn + (i + j) % a.bn;
+      return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
+    }
+    case 1: {  // DIAG: Eq. 5 over max(m,n) slots
+      if (s >= a.width) return 0.0;
+      const int row = s % a.bm, col = (k + s) % a.bn;
+      return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
+    }
+    case 2: {  // ROW: row k in slots 0..n-1
+      return (s < a.n && k < a.m) ? a.X[(size_t)k * a.ld + s] : 0.0;
+    }
+    case 3: {  // CTMAT: W (n x n_out); plaintext k = i * n_out_cts + kc
+      const int i = k / a.n_out_cts, kc = k % a.n_out_cts;
+      const int blk = s / a.width, j = s % a.width;
+      if (blk >= a.pack) return 0.0;
+      const int r = (i + j) % a.bn, col = kc * a.pack + blk;
+      return (r < a.n && col < a.n_out) ? a.X[(size_t)r * a.ld + col] : 0.0;
+    }
+  }
+  return 0.0;
+}
+
+// value of slot t of input ciphertext c (the encrypted operand)
+__device__ __forceinline__ double ct_slot_value(const EncodeArgs& a, int c, int t) {
+  switch (a.kind) {
+    case 0: {  // HYBRID: column block c of y, period bn
+      const int col = c * a.bn + (t % a.bn);
+      return col < a.n ? a.X[col] : 0.0;
+    }
+    case 1:
+    case 2: {  // DIAG / ROW: y with period n_pad
+      const int col = t % a.bn;
+      return col < a.n ? a.X[col] : 0.0;
+    }
+    case 3: {  // CTMAT: diagonal c of A (m x n), replicated over pack blocks
+      const int blk = t / a.width, j = t % a.width;
+      if (blk >= a.pack) return 0.0;
+      const int row = j % a.bm, col = (c + j) % a.bn;
+      return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
+    }
+  }
+  return 0.0;
+}
+
+// slots -> LDS FFT -> rounded coefficients in registers (mreg[2u] = m_k,
+// mreg[2u+1] = m_(k+N/2), k = tid + u T)
+template <int LOGN, bool CT>
+__device__ __forceinline__ void encode_to_regs(const EncodeArgs& a, int k, double2* z, double* mreg, const EncTabs& et,
+                                               double scale) {
+  constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T, PH = M / T;
+  const int tid = threadIdx.x;
+  for (int s = tid; s < M; s += T) {
+    const double v = CT ? ct_slot_value(a, k, s) : pt_slot_value(a, k, s);
+    z[et.slot2f[s]] = make_double2(v * scale, 0.0);
+  }
+  __syncthreads();
+  fft_dif_lds<LOGN>(z, et.fft_tw, false);
+  const double inv_m = 1.0 / (double)M;
+#pragma unroll
+  for (int u = 0; u < PH; ++u) {
+    const int kk = tid + u * T;
+    const double2 w = cmul(z[brev(kk, LOGN - 1)], cconj(et.twist[kk]));
+    mreg[2 * u] = round_half_away(w.x * inv_m);
+    mreg[2 * u + 1] = round_half_away(w.y * inv_m);
+  }
+  __syncthreads();
+}
+
+// One workgroup per plaintext: pack, encode, then every limb reduced and
+// transformed.  out[k][limb][N].
+template <int LOGN>
+__global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_pt(EncodeArgs a, EncTabs et, LimbMap map, DevTabs tb,
+                                                                 double* __restrict__ out) {
+  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PH = N / 2 / T;
+  __shared__ double2 s2[N / 2];
+  double* s = (double*)s2;
+  const int k = blockIdx.x;
+  double mreg[2 * PH];
+  const double scale = (a.kind == 2 && k == a.m) ? a.ind_scale : a.scale;
+  if (a.kind == 2 && k == a.m) {
+    // ROW indicator plaintext: 1 in slot 0 at scale q_(l-1)
+    for (int t = threadIdx.x; t < N / 2; t += T) ((double2*)s)[et.slot2f[t]] = make_double2(t == 0 ? scale : 0.0, 0.0);
+    __syncthreads();
+    fft_dif_lds<LOGN>((double2*)s, et.fft_tw, false);
+    const double inv_m = 1.0 / (double)(N / 2);
+#pragma unroll
+    for (int u = 0; u < PH; ++u) {
+      const int kk = threadIdx.x + u * T;
+      const double2 w = cmul(((double2*)s)[brev(kk, LOGN - 1)], cconj(et.twist[kk]));
+      mreg[2 * u] = round_half_away(w.x * inv_m);
+      mreg[2 * u + 1] = round_half_away(w.y * inv_m);
+    }
+    __syncthreads();
+  } else {
+    encode_to_regs<LOGN, false>(a, k, (double2*)s, mreg, et, scale);
+  }
+  for (int l = 0; l < map.n; ++l) {
+    const int pi = map.idx[l];
+    const ModQ m = tb.mods[pi];
+#pragma unroll
+    for (int u = 0; u < PH; ++u) {
+      const int kk = threadIdx.x + u * T;
+      s[kk] = reduce(mreg[2 * u], m);
+      s[kk + N / 2] = reduce(mreg[2 * u + 1], m);
+    }
+    __syncthreads();
+    ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)pi * N, m);
+    double* dst = out + ((size_t)k * map.n + l) * N;
+    for (int t = threadIdx.x; t < N; t += T) dst[t] = reduce(s[tb.perm[t]], m);
+    __syncthreads();
+  }
+}
+
+// Input ciphertext messages: one workgroup per ciphertext, int64 coefficients
+template <int LOGN>
+__global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_ct_msg(EncodeArgs a, EncTabs et, int64_t* __restrict__ msg) {
+  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PH = N / 2 / T;
+  __shared__ double2 s2[N / 2];
+  double* s = (double*)s2;
+  const int c = blockIdx.x;
+  double mreg[2 * PH];
+  encode_to_regs<LOGN, true>(a, c, (double2*)s, mreg, et, a.scale);
+  int64_t* dst = msg + (size_t)c * N;
+#pragma unroll
+  for (int u = 0; u < PH; ++u) {
+    const int kk = threadIdx.x + u * T;
+    dst[kk] = (int64_t)mreg[2 * u];
+    dst[kk + N / 2] = (int64_t)mreg[2 * u + 1];
+  }
+}
+
+// Decode: centred CRT lift (Garner mixed radix) of decrypted coefficient
+// residues [nct][l+1][N] (canonical, binary64), twist, DFT with sign +1,
+// slots z[c][j] = Re(.)/scale.
+template <int LOGN>
+__global__ __launch_bounds__(NttShape<LOGN>::T) void k_decode(const double* __restrict__ res, int lv, CrtTabs ct,
+                                                              EncTabs et, double inv_scale, double* __restrict__ z) {
+  constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T;
+  __shared__ double2 w[N / 2];
+  const int c = blockIdx.x;
+  const double* base = res + (size_t)c * (lv + 1) * N;
+  const int nl = lv + 1;
+  for (int k = threadIdx.x; k < M; k += T) {
+    double val[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kk = k + h * M;
+      double v[kMaxLimbs];
+      for (int i = 0; i < nl; ++i) {
+        const ModQ m = ct.mods[i];
+        double x = base[(size_t)i * N + kk];
+        for (int j = 0; j < i; ++j) x = mulmod(x - v[j], ct.garner_inv[j * kMaxLimbs + i], m);
+        v[i] = canon(x, m);
+      }
+      // sign: compare with the mixed-radix digits of (Q-1)/2 from the top
+      int cmp = 0;
+      for (int i = nl - 1; i >= 0 && cmp == 0; --i) {
+        const double h2 = 0.5 * (ct.mods[i].q - 1.0);
+        cmp = (v[i] > h2) ? 1 : ((v[i] < h2) ? -1 : 0);
+      }
+      double acc = (cmp > 0) ? v[nl - 1] - ct.mods[nl - 1].q : v[nl - 1];
+      for (int i = nl - 2; i >= 0; --i) acc = acc * ct.mods[i].q + v[i];
+      val[h] = acc;
+    }
+    w[k] = cmul(make_double2(val[0], val[1]), et.twist[k]);
+  }
+  __syncthreads();
+  fft_dif_lds<LOGN>(w, et.fft_tw, true);
+  for (int j = threadIdx.x; j < M; j += T) z[(size_t)c * M + j] = w[brev(et.slot2f[j], LOGN - 1)].x * inv_scale;
+}
+
+// lazy rotate-and-sum / read-out of the decoded slots (Sec. 4.3)
+__global__ __launch_bounds__(256) void k_readout(const double* __restrict__ z, EncodeArgs a, int ras_in_ct,
+                                                 double* __restrict__ y) {
+  const int M = a.slots;
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  switch (a.kind) {
+    case 0: {
+      if (idx >= a.m) return;
+      const int b = idx / a.bm, rr = idx % a.bm, g = rr / a.mprime, rho = rr % a.mprime;
+      const double* zb = z + (size_t)b * M;
+      double acc = 0.0;
+      for (int t = 0; t < a.bn / a.mprime; ++t) acc += zb[g * a.bn + rho + t * a.mprime];
+      y[idx] = acc;
+      return;
+    }
+    case 1: {
+      if (idx >= a.m) return;
+      if (a.bm >= a.bn || ras_in_ct) { y[idx] = z[idx]; return; }
+      double acc = 0.0;
+      for (int t = 0; t < a.bn / a.bm; ++t) acc += z[idx + t * a.bm];
+      y[idx] = acc;
+      return;
+    }
+    case 2:
+      if (idx < a.m) y[idx] = z[idx];
+      return;
+    case 3: {
+      if (idx >= a.m * a.n_out) return;
+      const int r = idx / a.n_out, col = idx % a.n_out;
+      const int kc = col / a.pack, blk = col % a.pack;
+      const double* zk = z + (size_t)kc * M + (size_t)blk * a.width;
+      if (a.bm >= a.bn) { y[idx] = zk[r]; return; }
+      double acc = 0.0;
+      for (int t = 0; t < a.bn / a.bm; ++t) acc += zk[r + t * a.bm];
+      y[idx] = acc;
+      return;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <int LOGN>
+static void encode_pt_impl(const LaunchCtx& L, const EncodeArgs& a, const EncTabs& et, LimbMap map, int count, double* out) {
+  hipLaunchKernelGGL(k_encode_pt<LOGN>, dim3(count), dim3(NttShape<LOGN>::T), 0, L.stream, a, et, map, L.tb, out);
+}
+template <int LOGN>
+static void encode_ct_impl(const LaunchCtx& L, const EncodeArgs& a, const EncTabs& et, int count, int64_t* msg) {
+  hipLaunchKernelGGL(k_encode_ct_msg<LOGN>, dim3(count), dim3(NttShape<LOGN>::T), 0, L.stream, a, et, msg);
+}
+template <int LOGN>
+static void decode_impl(const LaunchCtx& L, const double* res, int nct, int lv, const CrtTabs& ct, const EncTabs& et,
+                        double inv_scale, double* z) {
+  hipLaunchKernelGGL(k_decode<LOGN>, dim3(nct), dim3(NttShape<LOGN>::T), 0, L.stream, res, lv, ct, et, inv_scale, z);
+}
+
+#define DISPATCH_LOGN(L, FN, ...)                         \
+  switch ((L).logN) {                                     \
+    case 12: FN<12>(__VA_ARGS__); break;                  \
+    case 13: FN<13>(__VA_ARGS__); break;                  \
+    case 14: FN<14>(__VA_ARGS__); break;                  \
+    default: return hipErrorInvalidValue;                 \
+  }
+
+hipError_t launch_encode_pt(const LaunchCtx& L, const EncodeArgs& a, const EncTabs& et, LimbMap map, int count,
+                            double* out) {
+  if (count <= 0) return hipSuccess;
+  DISPATCH_LOGN(L, encode_pt_impl, L, a, et, map, count, out);
+  return hipGetLastError();
+}
+hipError_t launch_encode_ct(const LaunchCtx& L, const EncodeArgs& a, const EncTabs& et, int count, int64_t* msg) {
+  DISPATCH_LOGN(L, encode_ct_impl, L, a, et, count, msg);
+  return hipGetLastError();
+}
+hipError_t launch_decode(const LaunchCtx& L, const double* res, int nct, int lv, const CrtTabs& ct, const EncTabs& et,
+                         double inv_scale, double* z) {
+  DISPATCH_LOGN(L, decode_impl, L, res, nct, lv, ct, et, inv_scale, z);
+  return hipGetLastError();
+}
+hipError_t launch_readout(const LaunchCtx& L, const double* z, const EncodeArgs& a, int ras_in_ct, int count, double* y) {
+  hipLaunchKernelGGL(k_readout, dim3((count + 255) / 256), dim3(256), 0, L.stream, z, a, ras_in_ct, y);
+  return hipGetLastError();
+}
+
+}  // namespace pvfl

@@ -85,6 +85,9 @@ def lib():
             "pvfl_rescale": [_VP, i32, _VP, _VP, _VP],
             "pvfl_ct_mul_pt": [_VP, i32, _VP, _VP, _VP, _VP],
             "pvfl_ct_add": [_VP, i32, _VP, _VP, _VP, _VP],
+            "pvfl_encode_pt": [_VP, _VP, ctypes.c_int64, _VP, _VP],
+            "pvfl_encrypt": [_VP, _VP, _VP, ctypes.c_int64, u64, _VP, _VP],
+            "pvfl_decrypt_decode": [_VP, _VP, _VP, _VP, _VP],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -243,6 +246,17 @@ class Plan(_Handle):
 
     def bytes(self, what: str) -> int:
         return int(getattr(lib(), "pvfl_bytes_" + what)(self.h))
+
+    def encode_pt(self, X, out):
+        """X: device float64 matrix (row-major, contiguous rows)."""
+        _check(lib().pvfl_encode_pt(self.h, _ptr(X), X.stride(0) if X.dim() == 2 else X.numel(), _ptr(out), _stream()))
+
+    def encrypt(self, sk, v, seed: int, out):
+        ld = v.stride(0) if v.dim() == 2 else v.numel()
+        _check(lib().pvfl_encrypt(self.h, sk.h, _ptr(v), ld, seed, _ptr(out), _stream()))
+
+    def decrypt_decode(self, sk, ct, out):
+        _check(lib().pvfl_decrypt_decode(self.h, sk.h, _ptr(ct), _ptr(out), _stream()))
 
     def matmul(self, ct, pt, keys, out, ws=None):
         ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
