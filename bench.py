@@ -1,0 +1,211 @@
+"""Benchmark of the packed-HE ciphertext x plaintext matrix product on one GPU.
+
+Workload (default): 64 independent products X_k^T [[r_k]] at ring degree 2^14
+with 4 ciphertext primes + 1 special prime, batch ~ logU[512, 4096] and
+features ~ logU[32, 2000] (seeded), X ~ N(0,1), r ~ U[-1,1].  One step is the
+whole path for all 64 products with inputs resident in HBM: plaintext packing
+and encoding, encryption of r_k, the encrypted product, decryption + decoding +
+lazy rotate-and-sum.  The metric is cleartext multiply-accumulates per second
+(sum over products of m*n, unpadded) per wall second of the step.
+
+Prints one JSON line.  --gpus > 1 is not supported (one process, one GPU).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(name, shapes, n_diag, seeds):
+    """The CPU oracle, untuned, on a bounded sample: the first `n_diag`
+    diagonals of product 0, whole path (encode, encrypt, lazy-ModDown product,
+    decrypt + decode).  Returns cleartext MAC/s of the sample."""
+    from oracle import oracle as O
+    from oracle import plans as PL
+    from paper_2405_00482_amd import workloads as W
+    prm = O.Params.from_dict(W.params_dict(name))
+    m, n = shapes[0]
+    XT, r = W.c3_inputs(0, shapes[0])
+    plan = PL.HybridPlan(m, n, prm.slots)
+    D = min(n_diag, plan.mprime)
+
+    class Trunc:
+        def terms(self):
+            return [t for t in plan.terms() if t[1] < D]
+
+    s = O.keygen(prm, seeds["sk"])
+    keys = {O.galois_rotl(i, prm.N): O.rotkey_gen(prm, s, O.galois_rotl(i, prm.N), seeds["rotkeys"])
+            for i in range(1, D)}
+    t0 = time.perf_counter()
+    pts = [O.encode(PL.hybrid_pt_slots(plan, XT, 0, 0, i), prm.N, prm.scale) for i in range(D)]
+    ct = O.encrypt(prm, s, PL.hybrid_ct_ints(prm, plan, r, prm.scale)[0], prm.L, seeds["enc"])
+    out = PL.hybrid_matmul(prm, Trunc(), [ct], pts, keys, True)[0]
+    z = O.decrypt_decode(prm, s, out, prm.scale ** 2)
+    PL.hybrid_lazy_ras(plan, [z])
+    dt = time.perf_counter() - t0
+    macs = m * n * D / plan.mprime
+    return {"value": macs / dt, "unit": "MAC/s", "cores": 1, "kind": "oracle",
+            "sample": f"product 0 ({m}x{n}, m'={plan.mprime}): first {D} diagonals, whole path, "
+                      f"{dt:.1f} s single-threaded; rotation-key generation excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--products", type=int, default=64)
+    ap.add_argument("--cpu-diagonals", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--group", type=int, default=2)
+    ap.add_argument("--vec", type=int, default=1)
+    ap.add_argument("--chunk", type=int, default=32)
+    ap.add_argument("--percall-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2405_00482_amd import pvfl
+    from paper_2405_00482_amd import workloads as W
+
+    name = "C3"
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    seeds = W.seeds(name)
+    d = W.params_dict(name)
+    ctx = pvfl.Context.from_dict(d, device=0)
+    shapes = W.c3_shapes(args.products)
+    log(f"[bench] {name}: {len(shapes)} products, N=2^{d['logN']}, primes {len(d['q'])}+{len(d['p'])}")
+    plans = [ctx.plan(pvfl.PLAN_HYBRID, m, n, lazy=True) for (m, n) in shapes]
+    gal = sorted(set(g for p in plans for g in p.galois()))
+    sk = ctx.keygen(seeds["sk"])
+    t0 = time.perf_counter()
+    keys = ctx.rotkeys(sk, gal, seeds["rotkeys"])
+    log(f"[bench] {len(gal)} rotation keys generated in {time.perf_counter() - t0:.2f} s")
+    f64 = dict(dtype=torch.float64, device=dev)
+    Xs, rs, pts, cts, outs, ys = [], [], [], [], [], []
+    for k, (m, n) in enumerate(shapes):
+        XT, r = W.c3_inputs(k, (m, n))
+        Xs.append(torch.from_numpy(XT).to(dev))
+        rs.append(torch.from_numpy(r).to(dev))
+        p = plans[k]
+        pts.append(torch.empty(p.bytes("pt") // 8, **f64))
+        cts.append(torch.empty(p.bytes("ct_in") // 8, **f64))
+        outs.append(torch.empty(p.bytes("ct_out") // 8, **f64))
+        ys.append(torch.empty(m, **f64))
+    ws = torch.empty(max(p.bytes("workspace") for p in plans) // 8 + 1, **f64)
+    macs = sum(m * n for (m, n) in shapes)
+    pt_gib = sum(t.numel() for t in pts) * 8 / 2 ** 30
+    log(f"[bench] {macs} cleartext MACs per step, {pt_gib:.2f} GiB of plaintexts")
+
+    batch = pvfl.Batch(ctx, plans, X=Xs, v=rs, pt=pts, ct=cts, out=outs, y=ys, keys=keys,
+                       group=args.group, chunk=args.chunk, vec=args.vec)
+    binfo = batch.info()
+    log(f"[bench] batch: {binfo['work_items']} work items, key stream {binfo['key_bytes'] / 2 ** 30:.2f} GiB, "
+        f"plaintexts {binfo['pt_bytes'] / 2 ** 30:.2f} GiB")
+    seed = seeds["enc"]
+
+    def step_batched():
+        batch.run(sk, seed, graph=not args.no_graph)
+
+    def step_percall():
+        for k, p in enumerate(plans):
+            p.encode_pt(Xs[k], pts[k])
+            p.encrypt(sk, rs[k], seed + k, cts[k])
+            p.matmul(cts[k], pts[k], keys, outs[k], ws)
+            p.decrypt_decode(sk, outs[k], ys[k])
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    for w in range(args.warmup):
+        step_batched()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    ms_per_step = timed(step_batched, args.steps)
+    log(f"[bench] batched{' (graph replay)' if not args.no_graph else ''}: {args.steps} steps, {ms_per_step:.3f} ms/step")
+    # correctness of the timed outputs
+    errs = []
+    for k in range(len(plans)):
+        got = ys[k].cpu().numpy()
+        ref = Xs[k].cpu().numpy() @ rs[k].cpu().numpy()
+        errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    log(f"[bench] max relative error over products: 2^{np.log2(max(errs)):.2f}")
+    assert max(errs) < 2.0 ** -20, "decrypted products miss the 2^-20 bound"
+
+    # per-kernel HIP-event timing: the same batched step, launched eagerly
+    ctx.timing_enable(True)
+    for cls in range(4):
+        ctx.timing_read(cls)
+    ms_instrumented = timed(lambda: batch.run(sk, seed, graph=False), args.steps)
+    ctx.timing_enable(False)
+    log(f"[bench] batched, eager with kernel timers: {ms_instrumented:.3f} ms/step")
+    classes = {pvfl.TIMING_DIAG: "fused_diagonal", pvfl.TIMING_ENCODE: "encode_pt",
+               pvfl.TIMING_MODUP: "modup", pvfl.TIMING_MODDOWN: "moddown"}
+    kt = {}
+    for cls, nm in classes.items():
+        tot_ms, n_launch, by = ctx.timing_read(cls)
+        kt[nm] = {"ms_per_step": tot_ms / args.steps, "launches": n_launch, "bytes": by, "total_ms": tot_ms}
+        log(f"[bench] {nm}: {tot_ms / args.steps:.3f} ms/step over {n_launch} launches, "
+            f"{by / max(tot_ms, 1e-9) / 1e6:.1f} GB/s algorithmic")
+    dom = max(kt, key=lambda k: kt[k]["total_ms"])
+    dk = kt[dom]
+    achieved = dk["bytes"] / (dk["total_ms"] * 1e-3) / 1e9 if dk["total_ms"] > 0 else 0.0
+    ms_percall = None
+    if args.percall_steps > 0:
+        ms_percall = timed(step_percall, args.percall_steps)
+        log(f"[bench] per-call form: {ms_percall:.3f} ms/step")
+
+    result = {
+        "metric": "encrypted MatMult cleartext MAC/s at N=2^14",
+        "value": macs / (ms_per_step * 1e-3),
+        "unit": "MAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"C3: {len(shapes)} products X^T[[r]], batch logU[512,4096], features logU[32,2000], "
+                               f"N=2^14, 4+1 primes, Delta=2^40, hybrid plan, lazy ModDown, batched form "
+                               f"(group {args.group}, chunk {args.chunk}, vec {args.vec}){'' if args.no_graph else ', HIP graph'}",
+                   "macs_per_step": macs, "max_rel_err": max(errs),
+                   "percall_ms_per_step": ms_percall, "instrumented_ms_per_step": ms_instrumented},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "kernels": {k: {"ms_per_step": v["ms_per_step"], "launches_per_step": v["launches"] / args.steps,
+                        "algorithmic_GBps": v["bytes"] / max(v["total_ms"] * 1e-3, 1e-12) / 1e9}
+                    for k, v in kt.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        result["cpu_baseline"] = cpu_baseline(name, shapes, args.cpu_diagonals, seeds)
+        log(f"[bench] cpu baseline: {result['cpu_baseline']['value']:.3e} MAC/s")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

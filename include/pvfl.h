@@ -194,6 +194,58 @@ pvfl_status pvfl_ct_mul_pt(pvfl_ctx* ctx, int32_t level, const void* ct_dev, con
                            void* stream);
 pvfl_status pvfl_ct_add(pvfl_ctx* ctx, int32_t level, const void* a_dev, const void* b_dev, void* out_dev, void* stream);
 
+/* Batched form: many independent products of uneven shapes sharing one
+ * context, level, plaintext scale and rotation-key set.  Every phase of the
+ * path runs as one launch over all products, and the fused rotation x
+ * diagonal kernel streams each rotation key once per group of `group`
+ * products (products are grouped by their diagonal count m').  Products must
+ * be lazy-ModDown HYBRID (or DIAG without in-ciphertext RaS) plans with one
+ * input and one output ciphertext.  The buffers named at creation are the
+ * caller's (arrays of `count` device pointers): X_dev[k] (row stride ldx[k]),
+ * v_dev[k] (the encrypted vector), pt_dev[k], ct_dev[k], out_dev[k] sized by
+ * the plan queries, y_dev[k] (m_k doubles); X_dev/v_dev/y_dev may be NULL when
+ * only pvfl_batch_matmul is used.  The batch owns its workspace.
+ * opts (NULL = defaults {2, 32, 1, 1}): see pvfl_batch_opts.
+ * pvfl_batch_encrypt: product k uses seed + k.
+ * pvfl_batch_run: encode, encrypt, matmul, decrypt in order; with use_graph
+ *   the sequence is captured once into a HIP graph (per sk and seed) and
+ *   replayed.  Kernel timing is not recorded inside a captured graph. */
+typedef struct {
+  int32_t group;        /* products sharing one key stream per work item: 1, 2 or 4 */
+  int32_t chunk;        /* diagonals per work item (one partial sum each), 1..1024 */
+  int32_t vec;          /* evaluation indices per thread: 1 or 2 */
+  int32_t chunk_major;  /* 1: work items ordered by diagonal chunk first, so that work items
+                           running together share rotation-key lines in L2; 0: product-major */
+} pvfl_batch_opts;
+typedef struct pvfl_batch pvfl_batch;
+pvfl_status pvfl_batch_create(pvfl_ctx* ctx, int32_t count, const pvfl_plan* const* plans,
+                              const double* const* X_dev, const int64_t* ldx, const double* const* v_dev,
+                              void* const* pt_dev, void* const* ct_dev, void* const* out_dev, double* const* y_dev,
+                              const pvfl_rotkeys* keys, const pvfl_batch_opts* opts, pvfl_batch** out);
+pvfl_status pvfl_batch_encode(pvfl_batch* batch, void* stream);
+pvfl_status pvfl_batch_encrypt(pvfl_batch* batch, const pvfl_sk* sk, uint64_t seed, void* stream);
+pvfl_status pvfl_batch_matmul(pvfl_batch* batch, void* stream);
+pvfl_status pvfl_batch_decrypt(pvfl_batch* batch, const pvfl_sk* sk, void* stream);
+pvfl_status pvfl_batch_run(pvfl_batch* batch, const pvfl_sk* sk, uint64_t seed, int32_t use_graph, void* stream);
+/* work items of the fused kernel and its algorithmic key / plaintext bytes */
+pvfl_status pvfl_batch_info(const pvfl_batch* batch, int64_t* n_work_items, double* key_bytes, double* pt_bytes);
+void pvfl_batch_destroy(pvfl_batch* batch);
+
+/* Optional kernel timing for measurement.  When enabled, every launch of the
+ * timed kernel classes is bracketed by HIP events recorded on the launch's
+ * stream; pvfl_timing_read waits for the recorded events of one class, returns
+ * the summed elapsed time, the launch count and the summed algorithmic bytes
+ * (each key, plaintext and ciphertext limb counted once per launch), and
+ * forgets them.  Timing adds an event pair per launch; leave it off otherwise. */
+enum {
+  PVFL_TIMING_DIAG = 0,    /* fused hoisted-rotation x diagonal kernel */
+  PVFL_TIMING_ENCODE = 1,  /* plaintext packing + encoding + NTTs */
+  PVFL_TIMING_MODUP = 2,   /* ModUp of an input ciphertext */
+  PVFL_TIMING_MODDOWN = 3  /* ModDown of an output ciphertext */
+};
+pvfl_status pvfl_timing_enable(pvfl_ctx* ctx, int32_t enable);
+pvfl_status pvfl_timing_read(pvfl_ctx* ctx, int32_t kernel_class, double* total_ms, int64_t* launches, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

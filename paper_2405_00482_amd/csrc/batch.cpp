@@ -1,0 +1,389 @@
+// Batched execution of many independent products (host side).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <vector>
+
+#include "batch.hpp"
+#include "capi_internal.hpp"
+
+using namespace pvfl;
+
+#define HIP_TRY(expr)                                          \
+  do {                                                         \
+    hipError_t _e = (expr);                                    \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);          \
+  } while (0)
+
+namespace pvfl {
+pvfl_status enc_tables_for(pvfl_ctx* c, EncTabs* et, CrtTabs* crt);  // codec.cpp
+EncodeArgs geometry_of(const pvfl_plan* p, const double* X, int64_t ld);  // codec.cpp
+}  // namespace pvfl
+
+struct pvfl_batch {
+  pvfl_ctx* ctx = nullptr;
+  const pvfl_rotkeys* keys = nullptr;
+  int count = 0, pg = 4, CH = 64, vec = 1, lv = 0, K = 0, beta = 0, max_rows = 0;
+  int n_enc_work = 0, n_work = 0, n_slots = 0;
+  double inv_scale = 1.0;
+  std::vector<void*> allocs;
+  BatchProd* prods = nullptr;
+  EncodeArgs* args_pt = nullptr;
+  EncodeArgs* args_ct = nullptr;
+  int2* enc_work = nullptr;
+  DiagGroup* groups = nullptr;
+  DiagWork* work = nullptr;
+  DiagTask* tasks = nullptr;
+  int n_tasks = 0;
+  const double** ct_tab = nullptr;
+  double** ct_out_tab = nullptr;
+  double** out_tab = nullptr;
+  double *digits = nullptr, *yup = nullptr, *pc = nullptr, *part = nullptr, *acc = nullptr, *ydown = nullptr;
+  double *res = nullptr, *z = nullptr;
+  int64_t* msg = nullptr;
+  double key_bytes = 0, key_bytes_min = 0, pt_bytes = 0;
+  // captured whole-step graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  const pvfl_sk* graph_sk = nullptr;
+  uint64_t graph_seed = 0;
+  hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
+  bool has_X = false, has_v = false, has_y = false;
+  ~pvfl_batch() {
+    if (graph_exec) hipGraphExecDestroy(graph_exec);
+    if (graph) hipGraphDestroy(graph);
+    if (cap_stream) hipStreamDestroy(cap_stream);
+    for (void* p : allocs) hipFree(p);
+  }
+};
+
+template <class T>
+static pvfl_status dev_alloc(pvfl_batch* b, size_t count, T** out) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(1, count) * sizeof(T)) != hipSuccess) return fail(PVFL_E_NOMEM, "batch allocation");
+  b->allocs.push_back(p);
+  *out = (T*)p;
+  return PVFL_OK;
+}
+template <class T>
+static pvfl_status dev_put(pvfl_batch* b, const std::vector<T>& v, T** out) {
+  pvfl_status st = dev_alloc(b, v.size(), out);
+  if (st != PVFL_OK) return st;
+  if (!v.empty() && hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(PVFL_E_DEVICE, "batch table upload");
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_batch_create(pvfl_ctx* c, int32_t count, const pvfl_plan* const* plans,
+                                         const double* const* X_dev, const int64_t* ldx, const double* const* v_dev,
+                                         void* const* pt_dev, void* const* ct_dev, void* const* out_dev,
+                                         double* const* y_dev, const pvfl_rotkeys* keys, const pvfl_batch_opts* opts,
+                                         pvfl_batch** out) {
+  const pvfl_batch_opts dflt{2, 32, 1, 1};
+  const pvfl_batch_opts o = opts ? *opts : dflt;
+  int group = o.group, chunk = o.chunk;
+  const int vec = o.vec, order_mode = o.chunk_major;
+  if (!c || !plans || !pt_dev || !ct_dev || !out_dev || !out || count < 1) return fail(PVFL_E_INVALID, "bad argument");
+  *out = nullptr;
+  if (group != 1 && group != 2 && group != 4) return fail(PVFL_E_INVALID, "group must be 1, 2 or 4");
+  if (vec != 1 && vec != 2) return fail(PVFL_E_INVALID, "vec must be 1 or 2");
+  if (chunk > 1024) return fail(PVFL_E_INVALID, "chunk must be at most 1024");
+  if (chunk < 1) return fail(PVFL_E_INVALID, "chunk must be positive");
+  std::unique_ptr<pvfl_batch> b(new pvfl_batch());
+  b->ctx = c;
+  b->keys = keys;
+  b->count = count;
+  b->pg = group;
+  b->vec = vec;
+  b->CH = chunk;
+  const pvfl_plan* p0 = plans[0];
+  b->lv = p0->lv;
+  b->K = p0->K;
+  b->beta = p0->beta;
+  if (b->beta > 4) return fail(PVFL_E_PLAN, "batched kernel supports up to 4 digits");
+  const int N = c->N;
+  std::vector<BatchProd> prods(count);
+  std::vector<EncodeArgs> apt(count), act(count);
+  std::vector<int2> encw;
+  std::vector<const double*> ct_tab(count);
+  std::vector<double*> ct_out_tab(count), out_tab(count);
+  for (int k = 0; k < count; ++k) {
+    const pvfl_plan* p = plans[k];
+    if (!p || p->ctx != c) return fail(PVFL_E_INVALID, "plan belongs to another context");
+    const bool ok_kind = p->opts.kind == PVFL_PLAN_HYBRID || (p->opts.kind == PVFL_PLAN_DIAG && p->ras_rots.empty());
+    if (!ok_kind || !p->opts.lazy_moddown || p->info.ct_in != 1 || p->info.ct_out != 1)
+      return fail(PVFL_E_PLAN, "batched products must be lazy HYBRID/DIAG plans with one input and one output ciphertext");
+    if (p->lv != b->lv) return fail(PVFL_E_LEVEL, "batched products must share the level");
+    if (p->pt_scale != p0->pt_scale) return fail(PVFL_E_PLAN, "batched products must share the plaintext scale");
+    if (!p->galois.empty()) {
+      if (!keys || keys->ctx != c) return fail(PVFL_E_NOKEY, "batch needs rotation keys");
+      for (uint32_t g : p->galois)
+        if (keys->slot_of_rot[c->log5[g]] < 0) return fail(PVFL_E_NOKEY, "missing rotation key");
+    }
+    BatchProd& B = prods[k];
+    B.ct = (const double*)ct_dev[k];
+    B.ct_out = (double*)ct_dev[k];
+    B.pt = (const double*)pt_dev[k];
+    B.pt_out = (double*)pt_dev[k];
+    B.out = (double*)out_dev[k];
+    B.y = y_dev ? y_dev[k] : nullptr;
+    B.mprime = p->info.mprime;
+    apt[k] = geometry_of(p, X_dev ? X_dev[k] : nullptr, ldx ? ldx[k] : p->info.n);
+    apt[k].scale = p->pt_scale;
+    act[k] = geometry_of(p, v_dev ? v_dev[k] : nullptr, p->info.n);
+    act[k].scale = std::pow(2.0, c->log2_scale);
+    for (int j = 0; j < p->info.n_pts; ++j) encw.push_back(make_int2(k, j));
+    ct_tab[k] = B.ct;
+    ct_out_tab[k] = B.ct_out;
+    out_tab[k] = B.out;
+    b->max_rows = std::max(b->max_rows, p->info.m);
+    b->pt_bytes += 8.0 * (double)p->info.n_pts * b->K * N;
+  }
+  b->inv_scale = std::pow(2.0, -p0->info.out_log2_scale);
+  b->has_X = X_dev != nullptr;
+  b->has_v = v_dev != nullptr;
+  b->has_y = y_dev != nullptr;
+  for (int k = 0; k < count; ++k) {
+    if ((X_dev && !X_dev[k]) || (v_dev && !v_dev[k]) || (y_dev && !y_dev[k]) || !pt_dev[k] || !ct_dev[k] || !out_dev[k])
+      return fail(PVFL_E_INVALID, "null buffer for product " + std::to_string(k));
+  }
+  // groups of products with similar m' (descending), chunked diagonal ranges
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int z) { return prods[a].mprime > prods[z].mprime; });
+  std::vector<DiagGroup> groups;
+  std::vector<DiagWork> work;
+  double key_reads = 0;
+  for (int g0 = 0; g0 < count; g0 += group) {
+    DiagGroup G{};
+    G.np = std::min(group, count - g0);
+    int mx = 0;
+    for (int u = 0; u < G.np; ++u) {
+      G.prod[u] = order[g0 + u];
+      mx = std::max(mx, prods[G.prod[u]].mprime);
+    }
+    for (int i0 = 0; i0 < mx; i0 += chunk) work.push_back(DiagWork{(int)groups.size(), i0, std::min(i0 + chunk, mx), 0});
+    key_reads += std::max(0, mx - 1);
+    groups.push_back(G);
+  }
+  b->key_bytes = key_reads * 8.0 * 2 * b->beta * b->K * N;
+  // algorithmic minimum: every distinct rotation key of the batch streamed once
+  {
+    int max_mp = 0;
+    for (int k = 0; k < count; ++k) max_mp = std::max(max_mp, prods[k].mprime);
+    b->key_bytes_min = std::max(0, max_mp - 1) * 8.0 * 2 * b->beta * b->K * N;
+  }
+  // Chunk-major order: work items of every group for diagonals [0, CH) first,
+  // then [CH, 2 CH), ...  Blocks are dispatched round-robin over the 8 XCDs by
+  // linear block index; the blocks of one (tile, limb) for consecutive work
+  // items are (N/256)*K apart, a multiple of 8, so they land on the same XCD
+  // and read the same rotation-key lines from its L2.
+  if (order_mode == 1)
+    std::stable_sort(work.begin(), work.end(), [](const DiagWork& a, const DiagWork& z) { return a.i0 < z.i0; });
+  // task list: for each chunk (in order), tile, limb: the work items of that
+  // chunk, so that consecutive tasks read the same rotation-key tile
+  std::vector<DiagTask> tasks;
+  {
+    const int ntile = N / (256 * vec);
+    size_t w0 = 0;
+    while (w0 < work.size()) {
+      size_t w1 = w0;
+      while (w1 < work.size() && work[w1].i0 == work[w0].i0) ++w1;
+      if (order_mode != 1) w1 = w0 + 1;
+      for (int tile = 0; tile < ntile; ++tile)
+        for (int r = 0; r < b->K; ++r)
+          for (size_t wi = w0; wi < w1; ++wi) tasks.push_back(DiagTask{(int)wi, tile, r, 0});
+      w0 = w1;
+    }
+  }
+  b->n_tasks = (int)tasks.size();
+  int slot = 0;
+  for (int k = 0; k < count; ++k) {
+    prods[k].part0 = slot;
+    slot += (prods[k].mprime + chunk - 1) / chunk;
+  }
+  b->n_slots = slot;
+  b->n_work = (int)work.size();
+  b->n_enc_work = (int)encw.size();
+  pvfl_status st;
+  if ((st = dev_put(b.get(), prods, &b->prods)) != PVFL_OK) return st;
+  if ((st = dev_put(b.get(), apt, &b->args_pt)) != PVFL_OK) return st;
+  if ((st = dev_put(b.get(), act, &b->args_ct)) != PVFL_OK) return st;
+  if ((st = dev_put(b.get(), encw, &b->enc_work)) != PVFL_OK) return st;
+  if ((st = dev_put(b.get(), groups, &b->groups)) != PVFL_OK) return st;
+  if ((st = dev_put(b.get(), work, &b->work)) != PVFL_OK) return st;
+  if ((st = dev_put(b.get(), tasks, &b->tasks)) != PVFL_OK) return st;
+  if ((st = dev_put(b.get(), ct_tab, &b->ct_tab)) != PVFL_OK) return st;
+  if ((st = dev_put(b.get(), ct_out_tab, &b->ct_out_tab)) != PVFL_OK) return st;
+  if ((st = dev_put(b.get(), out_tab, &b->out_tab)) != PVFL_OK) return st;
+  const size_t KN = (size_t)b->K * N, Q = (size_t)(b->lv + 1) * N;
+  if ((st = dev_alloc(b.get(), (size_t)count * b->beta * KN, &b->digits)) != PVFL_OK) return st;
+  if ((st = dev_alloc(b.get(), (size_t)count * Q, &b->yup)) != PVFL_OK) return st;
+  if ((st = dev_alloc(b.get(), (size_t)count * 2 * Q, &b->pc)) != PVFL_OK) return st;
+  if ((st = dev_alloc(b.get(), (size_t)slot * 2 * KN, &b->part)) != PVFL_OK) return st;
+  if ((st = dev_alloc(b.get(), (size_t)count * 2 * KN, &b->acc)) != PVFL_OK) return st;
+  if ((st = dev_alloc(b.get(), (size_t)count * 2 * c->alpha * N, &b->ydown)) != PVFL_OK) return st;
+  if ((st = dev_alloc(b.get(), (size_t)count * N, &b->msg)) != PVFL_OK) return st;
+  if ((st = dev_alloc(b.get(), (size_t)count * Q, &b->res)) != PVFL_OK) return st;
+  if ((st = dev_alloc(b.get(), (size_t)count * (N / 2), &b->z)) != PVFL_OK) return st;
+  *out = b.release();
+  return PVFL_OK;
+}
+
+extern "C" void pvfl_batch_destroy(pvfl_batch* b) { delete b; }
+
+extern "C" pvfl_status pvfl_batch_encode(pvfl_batch* b, void* stream) {
+  if (!b) return fail(PVFL_E_INVALID, "null argument");
+  if (!b->has_X) return fail(PVFL_E_INVALID, "batch was created without plaintext matrices");
+  pvfl_ctx* c = b->ctx;
+  EncTabs et;
+  CrtTabs crt;
+  pvfl_status st = enc_tables_for(c, &et, &crt);
+  if (st != PVFL_OK) return st;
+  KernelTimer kt(c, stream, PVFL_TIMING_ENCODE, b->pt_bytes);
+  HIP_TRY(launch_encode_pt_batch(launch_ctx(c, stream), b->args_pt, b->enc_work, b->n_enc_work, b->prods, et,
+                                 qp_map(c, b->lv, true)));
+  kt.stop();
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_batch_encrypt(pvfl_batch* b, const pvfl_sk* sk, uint64_t seed, void* stream) {
+  if (!b || !sk) return fail(PVFL_E_INVALID, "null argument");
+  if (!b->has_v) return fail(PVFL_E_INVALID, "batch was created without input vectors");
+  pvfl_ctx* c = b->ctx;
+  EncTabs et;
+  CrtTabs crt;
+  pvfl_status st = enc_tables_for(c, &et, &crt);
+  if (st != PVFL_OK) return st;
+  LaunchCtx L = launch_ctx(c, stream);
+  HIP_TRY(launch_encode_ct_batch(L, b->args_ct, b->count, et, b->msg));
+  HIP_TRY(launch_encrypt(L, b->msg, b->count, sk->s, seed, b->lv, nullptr, b->ct_out_tab));
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_batch_matmul(pvfl_batch* b, void* stream) {
+  if (!b) return fail(PVFL_E_INVALID, "null argument");
+  pvfl_ctx* c = b->ctx;
+  const int N = c->N, lv = b->lv, K = b->K;
+  const size_t KN = (size_t)K * N, Q = (size_t)(lv + 1) * N;
+  const KsLevel& kl = c->ks_host[lv];
+  LaunchCtx L = launch_ctx(c, stream);
+  {
+    KernelTimer kt(c, stream, PVFL_TIMING_MODUP, 8.0 * (double)b->count * (Q + (size_t)b->beta * KN));
+    HIP_TRY(launch_modup(L, nullptr, 0, b->count, lv, c->ks_dev + lv, kl.n_tasks, b->yup, b->digits,
+                         (size_t)b->beta * KN, b->ct_tab));
+    kt.stop();
+  }
+  HIP_TRY(launch_scale_by_p(L, nullptr, lv, N, c->pmod_dev, b->pc, b->count, b->ct_tab));
+  BatchDiagArgs a{};
+  a.N = N;
+  a.K = K;
+  a.lv = lv;
+  a.CH = b->CH;
+  a.mods = c->tabs.mods;
+  const LimbMap lp = qp_map(c, lv, true);
+  for (int r = 0; r < K; ++r) a.limb_prime[r] = a.key_limb[r] = lp.idx[r];
+  a.prods = b->prods;
+  a.groups = b->groups;
+  a.work = b->work;
+  a.tasks = b->tasks;
+  a.n_tasks = b->n_tasks;
+  a.per_xcd = (b->n_tasks + 7) / 8;
+  if (b->keys) {
+    a.keys = b->keys->keys;
+    a.key_limbs = b->keys->key_limbs;
+    a.key_stride = b->keys->key_stride;
+    a.slot_of_rot = b->keys->slot_of_rot_dev;
+  }
+  a.digits = b->digits;
+  a.dig_stride = (size_t)b->beta * KN;
+  a.pc = b->pc;
+  a.pc_stride = 2 * Q;
+  a.part = b->part;
+  {
+    // algorithmic bytes: each distinct rotation key once, every plaintext once, digits and P*c once,
+    // partial sums written once
+    const double bytes = b->key_bytes_min + b->pt_bytes + 8.0 * (double)b->count * ((size_t)b->beta * KN + 2 * Q) +
+                         8.0 * (double)b->n_slots * 2 * KN;
+    KernelTimer kt(c, stream, PVFL_TIMING_DIAG, bytes);
+    HIP_TRY(launch_diag_batch(L, a, b->pg, b->beta, b->vec));
+    kt.stop();
+  }
+  HIP_TRY(launch_sum_partials_batch(L, b->part, b->prods, b->count, b->CH, K, N, lp, b->acc));
+  {
+    KernelTimer kt(c, stream, PVFL_TIMING_MODDOWN, 8.0 * (double)b->count * (2 * KN + 2 * Q));
+    HIP_TRY(launch_moddown(L, b->acc, 2 * b->count, lv, c->alpha, c->ks_dev + lv, b->ydown, nullptr, b->out_tab));
+    kt.stop();
+  }
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_batch_decrypt(pvfl_batch* b, const pvfl_sk* sk, void* stream) {
+  if (!b || !sk) return fail(PVFL_E_INVALID, "null argument");
+  if (!b->has_y) return fail(PVFL_E_INVALID, "batch was created without result buffers");
+  pvfl_ctx* c = b->ctx;
+  EncTabs et;
+  CrtTabs crt;
+  pvfl_status st = enc_tables_for(c, &et, &crt);
+  if (st != PVFL_OK) return st;
+  LaunchCtx L = launch_ctx(c, stream);
+  HIP_TRY(launch_decrypt_f64(L, nullptr, b->count, sk->s, b->lv, b->res, (const double* const*)b->out_tab));
+  HIP_TRY(launch_decode(L, b->res, b->count, b->lv, crt, et, b->inv_scale, b->z));
+  HIP_TRY(launch_readout_batch(L, b->z, b->args_ct, b->prods, b->count, b->max_rows, c->N / 2));
+  return PVFL_OK;
+}
+
+static pvfl_status run_phases(pvfl_batch* b, const pvfl_sk* sk, uint64_t seed, void* stream) {
+  pvfl_status st;
+  if ((st = pvfl_batch_encode(b, stream)) != PVFL_OK) return st;
+  if ((st = pvfl_batch_encrypt(b, sk, seed, stream)) != PVFL_OK) return st;
+  if ((st = pvfl_batch_matmul(b, stream)) != PVFL_OK) return st;
+  return pvfl_batch_decrypt(b, sk, stream);
+}
+
+extern "C" pvfl_status pvfl_batch_run(pvfl_batch* b, const pvfl_sk* sk, uint64_t seed, int32_t use_graph,
+                                      void* stream) {
+  if (!b || !sk) return fail(PVFL_E_INVALID, "null argument");
+  if (!use_graph) return run_phases(b, sk, seed, stream);
+  if (!b->has_X || !b->has_v || !b->has_y) return fail(PVFL_E_INVALID, "batch was created without input/output buffers");
+  if (!b->graph_exec || b->graph_sk != sk || b->graph_seed != seed) {
+    if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+    pvfl_status st = enc_tables_for(b->ctx, nullptr, nullptr);  // tables are created outside the capture
+    if (st != PVFL_OK) return st;
+    if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    const bool timing = b->ctx->timing_on;
+    b->ctx->timing_on = false;  // no event records inside the captured graph
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    st = run_phases(b, sk, seed, b->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    b->ctx->timing_on = timing;
+    if (st != PVFL_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
+    b->graph_sk = sk;
+    b->graph_seed = seed;
+  }
+  HIP_TRY(hipGraphLaunch(b->graph_exec, (hipStream_t)stream));
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_batch_info(const pvfl_batch* b, int64_t* n_work_items, double* key_bytes,
+                                       double* pt_bytes) {
+  if (!b) return fail(PVFL_E_INVALID, "null argument");
+  if (n_work_items) *n_work_items = b->n_work;
+  if (key_bytes) *key_bytes = b->key_bytes;
+  if (pt_bytes) *pt_bytes = b->pt_bytes;
+  return PVFL_OK;
+}

@@ -94,6 +94,10 @@ static int bit_reverse(int x, int bits) {
 // context
 // ---------------------------------------------------------------------------
 pvfl_ctx::~pvfl_ctx() {
+  for (auto& t : timed) {
+    hipEventDestroy(t.start);
+    hipEventDestroy(t.stop);
+  }
   if (enc_tabs && enc_tabs_free) enc_tabs_free(enc_tabs);
   if (scratch) hipFree(scratch);
   for (void* p : dev_allocs) hipFree(p);
@@ -417,7 +421,7 @@ extern "C" pvfl_status pvfl_encrypt_coeffs(pvfl_ctx* c, const pvfl_sk* sk, int32
                                            uint64_t seed, void* ct, void* stream) {
   if (!c || !sk || !m || !ct) return fail(PVFL_E_INVALID, "null argument");
   if (bad_level(c, level)) return fail(PVFL_E_LEVEL, "level out of range");
-  HIP_TRY(launch_encrypt(launch_ctx(c, stream), m, sk->s, seed, level, (double*)ct));
+  HIP_TRY(launch_encrypt(launch_ctx(c, stream), m, 1, sk->s, seed, level, (double*)ct));
   return PVFL_OK;
 }
 
@@ -494,12 +498,12 @@ extern "C" pvfl_status pvfl_rotate(pvfl_ctx* c, const pvfl_rotkeys* keys, int32_
   double* out = (double*)out_v;
   LaunchCtx L = launch_ctx(c, stream);
   if (hoisted) {
-    HIP_TRY(launch_modup(L, ct + Q, level, c->ks_dev + level, kl.n_tasks, yup, digits));
+    HIP_TRY(launch_modup(L, ct, 0, 1, level, c->ks_dev + level, kl.n_tasks, yup, digits, 0));
     if ((st = keyswitch_digits(c, keys, level, digits, rot, rot, u, ydown, v, stream)) != PVFL_OK) return st;
     HIP_TRY(launch_automorph(L, ct, level + 1, N, rot, rct));
   } else {
     HIP_TRY(launch_automorph(L, ct, 2 * (level + 1), N, rot, rct));
-    HIP_TRY(launch_modup(L, rct + Q, level, c->ks_dev + level, kl.n_tasks, yup, digits));
+    HIP_TRY(launch_modup(L, rct, 0, 1, level, c->ks_dev + level, kl.n_tasks, yup, digits, 0));
     if ((st = keyswitch_digits(c, keys, level, digits, 0, rot, u, ydown, v, stream)) != PVFL_OK) return st;
   }
   // out = (phi(c0) + v0, v1)
@@ -527,5 +531,40 @@ extern "C" pvfl_status pvfl_ct_add(pvfl_ctx* c, int32_t level, const void* a, co
   if (!c || !a || !b || !out) return fail(PVFL_E_INVALID, "null argument");
   if (bad_level(c, level)) return fail(PVFL_E_LEVEL, "level out of range");
   HIP_TRY(launch_ct_add(launch_ctx(c, stream), (const double*)a, (const double*)b, level, c->N, (double*)out));
+  return PVFL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+extern "C" pvfl_status pvfl_timing_enable(pvfl_ctx* c, int32_t enable) {
+  if (!c) return fail(PVFL_E_INVALID, "null argument");
+  c->timing_on = enable != 0;
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_timing_read(pvfl_ctx* c, int32_t cls, double* total_ms, int64_t* launches, double* bytes) {
+  if (!c || !total_ms || !launches || !bytes) return fail(PVFL_E_INVALID, "null argument");
+  double ms = 0, by = 0;
+  int64_t n = 0;
+  std::vector<pvfl_ctx::Timed> keep;
+  for (auto& t : c->timed) {
+    if (t.cls != cls) {
+      keep.push_back(t);
+      continue;
+    }
+    HIP_TRY(hipEventSynchronize(t.stop));
+    float e = 0;
+    HIP_TRY(hipEventElapsedTime(&e, t.start, t.stop));
+    ms += e;
+    by += t.bytes;
+    ++n;
+    hipEventDestroy(t.start);
+    hipEventDestroy(t.stop);
+  }
+  c->timed.swap(keep);
+  *total_ms = ms;
+  *launches = n;
+  *bytes = by;
   return PVFL_OK;
 }

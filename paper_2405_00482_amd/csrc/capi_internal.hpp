@@ -37,6 +37,14 @@ struct pvfl_ctx {
   // encoder tables (slot <-> FFT index, twiddles), created on first use
   void* enc_tabs = nullptr;
   void (*enc_tabs_free)(void*) = nullptr;
+  // optional per-launch timing (HIP events on the launch stream)
+  struct Timed {
+    hipEvent_t start, stop;
+    int cls;
+    double bytes;
+  };
+  bool timing_on = false;
+  std::vector<Timed> timed;
   ~pvfl_ctx();
 };
 
@@ -85,6 +93,28 @@ struct pvfl_plan {
 };
 
 namespace pvfl {
+// Brackets one kernel launch with HIP events when timing is enabled.
+struct KernelTimer {
+  pvfl_ctx* c;
+  hipStream_t s;
+  int cls;
+  double bytes;
+  hipEvent_t a = nullptr;
+  KernelTimer(pvfl_ctx* c_, void* stream, int cls_, double bytes_) : c(c_), s((hipStream_t)stream), cls(cls_), bytes(bytes_) {
+    if (c->timing_on && hipEventCreate(&a) == hipSuccess) hipEventRecord(a, s);
+  }
+  void stop() {
+    if (!a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) == hipSuccess) {
+      hipEventRecord(b, s);
+      c->timed.push_back(pvfl_ctx::Timed{a, b, cls, bytes});
+    } else {
+      hipEventDestroy(a);
+    }
+    a = nullptr;
+  }
+};
 LimbMap qp_map(const pvfl_ctx* c, int lv, bool with_p);
 LimbMap key_limb_map(const pvfl_ctx* c, int lv);
 LaunchCtx launch_ctx(const pvfl_ctx* c, void* stream);

@@ -76,7 +76,10 @@ pvfl_status enc_tables(pvfl_ctx* c, EncHost** out) {
   return PVFL_OK;
 }
 
-EncodeArgs plan_geometry(const pvfl_plan* p, const double* X, int64_t ld) {
+}  // namespace
+
+namespace pvfl {
+EncodeArgs geometry_of(const pvfl_plan* p, const double* X, int64_t ld) {
   EncodeArgs a{};
   const pvfl_plan_info& I = p->info;
   a.kind = I.kind;
@@ -98,7 +101,16 @@ EncodeArgs plan_geometry(const pvfl_plan* p, const double* X, int64_t ld) {
   }
   return a;
 }
-}  // namespace
+
+pvfl_status enc_tables_for(pvfl_ctx* c, EncTabs* et, CrtTabs* crt) {
+  EncHost* h;
+  pvfl_status st = enc_tables(c, &h);
+  if (st != PVFL_OK) return st;
+  if (et) *et = h->et;
+  if (crt) *crt = h->crt;
+  return PVFL_OK;
+}
+}  // namespace pvfl
 
 extern "C" pvfl_status pvfl_encode_pt(const pvfl_plan* p, const double* X, int64_t ld, void* pt, void* stream) {
   if (!p || !X || !pt) return fail(PVFL_E_INVALID, "null argument");
@@ -108,11 +120,13 @@ extern "C" pvfl_status pvfl_encode_pt(const pvfl_plan* p, const double* X, int64
   EncHost* h;
   pvfl_status st = enc_tables(c, &h);
   if (st != PVFL_OK) return st;
-  EncodeArgs a = plan_geometry(p, X, ld);
+  EncodeArgs a = geometry_of(p, X, ld);
   a.scale = p->pt_scale;
   if (p->info.kind == PVFL_PLAN_ROW) a.ind_scale = (double)c->primes[p->lv - 1];
   LimbMap map = qp_map(c, p->lv, p->info.pt_limbs > p->lv + 1);
+  KernelTimer kt(c, stream, PVFL_TIMING_ENCODE, 8.0 * (double)p->info.n_pts * map.n * c->N);
   HIP_TRY(launch_encode_pt(launch_ctx(c, stream), a, h->et, map, p->info.n_pts, (double*)pt));
+  kt.stop();
   return PVFL_OK;
 }
 
@@ -128,12 +142,11 @@ extern "C" pvfl_status pvfl_encrypt(const pvfl_plan* p, const pvfl_sk* sk, const
   double* scratch;
   if ((st = ctx_scratch(c, sizeof(int64_t) * (size_t)nct * N, &scratch)) != PVFL_OK) return st;
   int64_t* msg = (int64_t*)scratch;
-  EncodeArgs a = plan_geometry(p, v, ld);
+  EncodeArgs a = geometry_of(p, v, ld);
   a.scale = std::pow(2.0, c->log2_scale);
   LaunchCtx L = launch_ctx(c, stream);
   HIP_TRY(launch_encode_ct(L, a, h->et, nct, msg));
-  for (int k = 0; k < nct; ++k)
-    HIP_TRY(launch_encrypt(L, msg + (size_t)k * N, sk->s, seed + (uint64_t)k, lv, (double*)ct + (size_t)k * 2 * (lv + 1) * N));
+  HIP_TRY(launch_encrypt(L, msg, nct, sk->s, seed, lv, (double*)ct));
   return PVFL_OK;
 }
 
@@ -151,7 +164,7 @@ extern "C" pvfl_status pvfl_decrypt_decode(const pvfl_plan* p, const pvfl_sk* sk
   LaunchCtx L = launch_ctx(c, stream);
   HIP_TRY(launch_decrypt_f64(L, (const double*)ct, nct, sk->s, lv, scratch));
   HIP_TRY(launch_decode(L, scratch, nct, lv, h->crt, h->et, std::pow(2.0, -p->info.out_log2_scale), scratch + res_n));
-  EncodeArgs a = plan_geometry(p, nullptr, 0);
+  EncodeArgs a = geometry_of(p, nullptr, 0);
   const int count = p->info.kind == PVFL_PLAN_CTMAT ? p->info.m * p->info.n_out : p->info.m;
   HIP_TRY(launch_readout(L, scratch + res_n, a, p->opts.ras_in_ct, count, y));
   return PVFL_OK;

@@ -12,169 +12,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "encode.hpp"
-#include "ntt_core.hpp"
+#include "encode_dev.hpp"
 
 namespace pvfl {
-
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-
-__device__ __forceinline__ double round_half_away(double x) {
-  const double r = __builtin_trunc(x + (x >= 0.0 ? 0.5 : -0.5));
-  return r;
-}
-
-// In-place DIF FFT over M = N/2 points in LDS, sign -1 (conj = false) or +1.
-template <int LOGN>
-__device__ __forceinline__ void fft_dif_lds(double2* a, const double2* __restrict__ tw, bool conj) {
-  constexpr int LOGM = LOGN - 1, M = 1 << LOGM;
-  constexpr int T = NttShape<LOGN>::T;
-  constexpr int BF = M / 2 / T;  // 4
-  const int tid = threadIdx.x;
-#pragma unroll 1
-  for (int s = 0; s < LOGM; ++s) {
-    const int lhalf = LOGM - 1 - s;   // log2 of half the current length
-    const int half = 1 << lhalf;
-#pragma unroll
-    for (int r = 0; r < BF; ++r) {
-      const int b = tid + r * T;
-      const int blk = b >> lhalf, j = b & (half - 1);
-      const int i0 = (blk << (lhalf + 1)) + j, i1 = i0 + half;
-      double2 w = tw[j << s];  // W_len^j = W_M^(j M/len)
-      if (conj) w = cconj(w);
-      const double2 u = a[i0], v = a[i1];
-      a[i0] = make_double2(u.x + v.x, u.y + v.y);
-      a[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
-    }
-    __syncthreads();
-  }
-}
-
-__device__ __forceinline__ int brev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
-
-// value of slot s of plaintext k for the plan (0 outside the matrix)
-__device__ __forceinline__ double pt_slot_value(const EncodeArgs& a, int k, int s) {
-  switch (a.kind) {
-    case 0: {  // HYBRID: block (b, c), diagonal i; slot s = g bn + j
-      const int per = a.col_blocks * a.mprime;
-      const int b = k / per, c = (k / a.mprime) % a.col_blocks, i = k % a.mprime;
-      const int g = s / a.bn, j = s % a.bn;
-      const int rr = g * a.mprime + (j % a.mprime);
-      if (rr >= a.bm) return 0.0;
-      const int row = b * a.bm + rr, col = c * a.bn + (i + j) % a.bn;
-      return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
-    }
-    case 1: {  // DIAG: Eq. 5 over max(m,n) slots
-      if (s >= a.width) return 0.0;
-      const int row = s % a.bm, col = (k + s) % a.bn;
-      return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
-    }
-    case 2: {  // ROW: row k in slots 0..n-1
-      return (s < a.n && k < a.m) ? a.X[(size_t)k * a.ld + s] : 0.0;
-    }
-    case 3: {  // CTMAT: W (n x n_out); plaintext k = i * n_out_cts + kc
-      const int i = k / a.n_out_cts, kc = k % a.n_out_cts;
-      const int blk = s / a.width, j = s % a.width;
-      if (blk >= a.pack) return 0.0;
-      const int r = (i + j) % a.bn, col = kc * a.pack + blk;
-      return (r < a.n && col < a.n_out) ? a.X[(size_t)r * a.ld + col] : 0.0;
-    }
-  }
-  return 0.0;
-}
-
-// value of slot t of input ciphertext c (the encrypted operand)
-__device__ __forceinline__ double ct_slot_value(const EncodeArgs& a, int c, int t) {
-  switch (a.kind) {
-    case 0: {  // HYBRID: column block c of y, period bn
-      const int col = c * a.bn + (t % a.bn);
-      return col < a.n ? a.X[col] : 0.0;
-    }
-    case 1:
-    case 2: {  // DIAG / ROW: y with period n_pad
-      const int col = t % a.bn;
-      return col < a.n ? a.X[col] : 0.0;
-    }
-    case 3: {  // CTMAT: diagonal c of A (m x n), replicated over pack blocks
-      const int blk = t / a.width, j = t % a.width;
-      if (blk >= a.pack) return 0.0;
-      const int row = j % a.bm, col = (c + j) % a.bn;
-      return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
-    }
-  }
-  return 0.0;
-}
-
-// slots -> LDS FFT -> rounded coefficients in registers (mreg[2u] = m_k,
-// mreg[2u+1] = m_(k+N/2), k = tid + u T)
-template <int LOGN, bool CT>
-__device__ __forceinline__ void encode_to_regs(const EncodeArgs& a, int k, double2* z, double* mreg, const EncTabs& et,
-                                               double scale) {
-  constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T, PH = M / T;
-  const int tid = threadIdx.x;
-  for (int s = tid; s < M; s += T) {
-    const double v = CT ? ct_slot_value(a, k, s) : pt_slot_value(a, k, s);
-    z[et.slot2f[s]] = make_double2(v * scale, 0.0);
-  }
-  __syncthreads();
-  fft_dif_lds<LOGN>(z, et.fft_tw, false);
-  const double inv_m = 1.0 / (double)M;
-#pragma unroll
-  for (int u = 0; u < PH; ++u) {
-    const int kk = tid + u * T;
-    const double2 w = cmul(z[brev(kk, LOGN - 1)], cconj(et.twist[kk]));
-    mreg[2 * u] = round_half_away(w.x * inv_m);
-    mreg[2 * u + 1] = round_half_away(w.y * inv_m);
-  }
-  __syncthreads();
-}
 
 // One workgroup per plaintext: pack, encode, then every limb reduced and
 // transformed.  out[k][limb][N].
 template <int LOGN>
 __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_pt(EncodeArgs a, EncTabs et, LimbMap map, DevTabs tb,
                                                                  double* __restrict__ out) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PH = N / 2 / T;
-  __shared__ double2 s2[N / 2];
-  double* s = (double*)s2;
-  const int k = blockIdx.x;
-  double mreg[2 * PH];
-  const double scale = (a.kind == 2 && k == a.m) ? a.ind_scale : a.scale;
-  if (a.kind == 2 && k == a.m) {
-    // ROW indicator plaintext: 1 in slot 0 at scale q_(l-1)
-    for (int t = threadIdx.x; t < N / 2; t += T) ((double2*)s)[et.slot2f[t]] = make_double2(t == 0 ? scale : 0.0, 0.0);
-    __syncthreads();
-    fft_dif_lds<LOGN>((double2*)s, et.fft_tw, false);
-    const double inv_m = 1.0 / (double)(N / 2);
-#pragma unroll
-    for (int u = 0; u < PH; ++u) {
-      const int kk = threadIdx.x + u * T;
-      const double2 w = cmul(((double2*)s)[brev(kk, LOGN - 1)], cconj(et.twist[kk]));
-      mreg[2 * u] = round_half_away(w.x * inv_m);
-      mreg[2 * u + 1] = round_half_away(w.y * inv_m);
-    }
-    __syncthreads();
-  } else {
-    encode_to_regs<LOGN, false>(a, k, (double2*)s, mreg, et, scale);
-  }
-  for (int l = 0; l < map.n; ++l) {
-    const int pi = map.idx[l];
-    const ModQ m = tb.mods[pi];
-#pragma unroll
-    for (int u = 0; u < PH; ++u) {
-      const int kk = threadIdx.x + u * T;
-      s[kk] = reduce(mreg[2 * u], m);
-      s[kk + N / 2] = reduce(mreg[2 * u + 1], m);
-    }
-    __syncthreads();
-    ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)pi * N, m);
-    double* dst = out + ((size_t)k * map.n + l) * N;
-    for (int t = threadIdx.x; t < N; t += T) dst[t] = reduce(s[tb.perm[t]], m);
-    __syncthreads();
-  }
+  __shared__ double2 s2[NttShape<LOGN>::LDS / 2];
+  encode_pt_body<LOGN>(a, (int)blockIdx.x, et, map, tb, s2, out + (size_t)blockIdx.x * map.n * (1 << LOGN));
 }
 
 // Input ciphertext messages: one workgroup per ciphertext, int64 coefficients
@@ -182,10 +30,9 @@ template <int LOGN>
 __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_ct_msg(EncodeArgs a, EncTabs et, int64_t* __restrict__ msg) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PH = N / 2 / T;
   __shared__ double2 s2[N / 2];
-  double* s = (double*)s2;
   const int c = blockIdx.x;
   double mreg[2 * PH];
-  encode_to_regs<LOGN, true>(a, c, (double2*)s, mreg, et, a.scale);
+  encode_to_regs<LOGN, true>(a, c, s2, mreg, et, a.scale);
   int64_t* dst = msg + (size_t)c * N;
 #pragma unroll
   for (int u = 0; u < PH; ++u) {

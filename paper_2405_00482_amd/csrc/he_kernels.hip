@@ -4,65 +4,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "he_dev.hpp"
 #include "kernels.hpp"
 #include "ntt_core.hpp"
 
 namespace pvfl {
 
-// ---------------------------------------------------------------------------
-// Philox4x32-10 counter-based generator (Salmon et al., SC'11) and samplers.
-// Word idx of stream `stream` under key `seed`: counter = (idx>>1, stream),
-// key = seed, word (0,1) for even idx and (2,3) for odd idx, low word first.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t philox_word(uint64_t seed, uint64_t stream, uint64_t idx) {
-  uint32_t c0 = (uint32_t)(idx >> 1), c1 = (uint32_t)(idx >> 33);
-  uint32_t c2 = (uint32_t)stream, c3 = (uint32_t)(stream >> 32);
-  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#pragma unroll
-  for (int round = 0; round < 10; ++round) {
-    if (round) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
-  }
-  return (idx & 1) ? ((uint64_t)c2 | ((uint64_t)c3 << 32)) : ((uint64_t)c0 | ((uint64_t)c1 << 32));
-}
-
-// floor(u * q / 2^64) for q < 2^49: the high 64 bits of a 64x64 product.
-__device__ __forceinline__ uint64_t mul_hi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
-
-__device__ __forceinline__ double sample_uniform_res(uint64_t seed, uint64_t stream, uint64_t idx, uint64_t q) {
-  return u64_to_f64(mul_hi64(philox_word(seed, stream, idx), q));
-}
-__device__ __forceinline__ int sample_ternary(uint64_t seed, uint64_t stream, uint64_t idx) {
-  return (int)mul_hi64(philox_word(seed, stream, idx), 3ull) - 1;
-}
-__device__ __forceinline__ int sample_cbd21(uint64_t seed, uint64_t stream, uint64_t idx) {
-  const uint64_t u = philox_word(seed, stream, idx);
-  return __popcll(u & 0x1FFFFFull) - __popcll((u >> 21) & 0x1FFFFFull);
-}
-
-__device__ __forceinline__ int orbit_shift(int t, int rot, int half) {
-  return (t & half) | ((t + rot) & (half - 1));
-}
-
-// ---------------------------------------------------------------------------
-// LDS staging helpers (orbit order <-> bit-reversed order)
-// ---------------------------------------------------------------------------
-template <int LOGN>
-__device__ __forceinline__ void store_orbit(const double* s, double* __restrict__ out, const uint32_t* __restrict__ perm, ModQ m) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  for (int t = threadIdx.x; t < N; t += T) out[t] = reduce(s[perm[t]], m);
-}
-template <int LOGN>
-__device__ __forceinline__ void load_orbit(double* s, const double* __restrict__ in, const uint32_t* __restrict__ perm, ModQ m) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  for (int t = threadIdx.x; t < N; t += T) s[perm[t]] = reduce(in[t], m);
-  __syncthreads();
-}
-
 #define NTT_KERNEL(LOGN) __global__ __launch_bounds__(NttShape<LOGN>::T)
+#define NTT_LDS(LOGN) __shared__ double s[NttShape<LOGN>::LDS]
 
 // ---------------------------------------------------------------------------
 // plain batched transforms over contiguous limbs.  Block b handles limb
@@ -70,56 +19,51 @@ __device__ __forceinline__ void load_orbit(double* s, const double* __restrict__
 // ---------------------------------------------------------------------------
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_ntt_fwd(const double* __restrict__ in, double* __restrict__ out, LimbMap map, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
-  const int b = blockIdx.x, l = b % map.n, pi = map.idx[l];
+  constexpr int N = 1 << LOGN;
+  NTT_LDS(LOGN);
+  const int b = blockIdx.x, pi = map.idx[b % map.n];
   const ModQ m = tb.mods[pi];
   const double* src = in + (size_t)b * N;
-  for (int k = threadIdx.x; k < N; k += T) s[k] = reduce(src[k], m);
-  __syncthreads();
-  ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)pi * N, m);
-  store_orbit<LOGN>(s, out + (size_t)b * N, tb.perm, m);
+  ntt_fwd<LOGN>(s, [&](int j) { return src[j]; }, tb.fwd_tw + (size_t)pi * N, m);
+  store_orbit<LOGN>(s, out + (size_t)b * N, tb.perm);
 }
 
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_ntt_inv(const double* __restrict__ in, double* __restrict__ out, LimbMap map, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
-  const int b = blockIdx.x, l = b % map.n, pi = map.idx[l];
+  constexpr int N = 1 << LOGN;
+  NTT_LDS(LOGN);
+  const int b = blockIdx.x, pi = map.idx[b % map.n];
   const ModQ m = tb.mods[pi];
-  load_orbit<LOGN>(s, in + (size_t)b * N, tb.perm, m);
-  ntt_inv_lds<LOGN>(s, tb.inv_tw + (size_t)pi * N, m, tb.ninv[pi]);
+  lds_from_orbit<LOGN>(s, in + (size_t)b * N, tb.perm, m);
   double* dst = out + (size_t)b * N;
-  for (int k = threadIdx.x; k < N; k += T) dst[k] = s[k];
+  ntt_inv<LOGN>(s, [&](int j, double v) { dst[j] = v; }, tb.inv_tw + (size_t)pi * N, m, tb.ninv[pi]);
 }
 
 // signed integer coefficients [count][N] -> evaluation-domain residues
 // [count][nl][N]: every limb of polynomial c is the same integer vector.
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_import_i64(const int64_t* __restrict__ in, double* __restrict__ out, LimbMap map, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
-  const int b = blockIdx.x, c = b / map.n, l = b % map.n, pi = map.idx[l];
+  constexpr int N = 1 << LOGN;
+  NTT_LDS(LOGN);
+  const int b = blockIdx.x, c = b / map.n, pi = map.idx[b % map.n];
   const ModQ m = tb.mods[pi];
   const double t32 = tb.two32[pi];
   const int64_t* src = in + (size_t)c * N;
-  for (int k = threadIdx.x; k < N; k += T) s[k] = i64_to_res(src[k], m, t32);
-  __syncthreads();
-  ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)pi * N, m);
-  store_orbit<LOGN>(s, out + (size_t)b * N, tb.perm, m);
+  ntt_fwd<LOGN>(s, [&](int j) { return i64_to_res(src[j], m, t32); }, tb.fwd_tw + (size_t)pi * N, m);
+  store_orbit<LOGN>(s, out + (size_t)b * N, tb.perm);
 }
 
 // evaluation-domain residues -> canonical coefficient residues as uint64
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_export_u64(const double* __restrict__ in, uint64_t* __restrict__ out, LimbMap map, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
-  const int b = blockIdx.x, l = b % map.n, pi = map.idx[l];
+  constexpr int N = 1 << LOGN;
+  NTT_LDS(LOGN);
+  const int b = blockIdx.x, pi = map.idx[b % map.n];
   const ModQ m = tb.mods[pi];
-  load_orbit<LOGN>(s, in + (size_t)b * N, tb.perm, m);
-  ntt_inv_lds<LOGN>(s, tb.inv_tw + (size_t)pi * N, m, tb.ninv[pi]);
+  lds_from_orbit<LOGN>(s, in + (size_t)b * N, tb.perm, m);
   uint64_t* dst = out + (size_t)b * N;
-  for (int k = threadIdx.x; k < N; k += T) dst[k] = f64_to_u64(canon(s[k], m));
+  ntt_inv<LOGN>(s, [&](int j, double v) { dst[j] = f64_to_u64(canon(v, m)); }, tb.inv_tw + (size_t)pi * N, m,
+                tb.ninv[pi]);
 }
 
 // ---------------------------------------------------------------------------
@@ -128,50 +72,50 @@ NTT_KERNEL(LOGN) void k_export_u64(const double* __restrict__ in, uint64_t* __re
 // secret key: ternary s, transformed for every prime of the context.
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_keygen(uint64_t seed, double* __restrict__ sk, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
+  constexpr int N = 1 << LOGN;
+  NTT_LDS(LOGN);
   const int pi = blockIdx.x;
   const ModQ m = tb.mods[pi];
-  for (int k = threadIdx.x; k < N; k += T) s[k] = (double)sample_ternary(seed, kStreamSecret, (uint64_t)k);
-  __syncthreads();
-  ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)pi * N, m);
-  store_orbit<LOGN>(s, sk + (size_t)pi * N, tb.perm, m);
+  ntt_fwd<LOGN>(s, [&](int j) { return (double)sample_ternary(seed, kStreamSecret, (uint64_t)j); },
+                tb.fwd_tw + (size_t)pi * N, m);
+  store_orbit<LOGN>(s, sk + (size_t)pi * N, tb.perm);
 }
 
 // secret-key encryption of integer coefficients m (c1 = a, c0 = -a s + m + e)
-// at level lv: block i handles limb i.
+// at level lv.  Block (c, i): ciphertext c, limb i; ciphertext c uses
+// msg[c] and seed + c.
 template <int LOGN>
-NTT_KERNEL(LOGN) void k_encrypt(const int64_t* __restrict__ msg, const double* __restrict__ sk, uint64_t seed,
-                                 int lv, double* __restrict__ ct, DevTabs tb) {
+NTT_KERNEL(LOGN) void k_encrypt(const int64_t* __restrict__ msg, const double* __restrict__ sk, uint64_t seed0,
+                                 int lv, double* __restrict__ ct_all, double* const* __restrict__ ct_tab, DevTabs tb) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PER = N / T;
-  __shared__ double s[N];
-  const int i = blockIdx.x;
+  NTT_LDS(LOGN);
+  const int i = blockIdx.x % (lv + 1), c = blockIdx.x / (lv + 1);
+  const uint64_t seed = seed0 + (uint64_t)c;
+  const int64_t* mc = msg + (size_t)c * N;
+  double* ct = ct_tab ? ct_tab[c] : ct_all + (size_t)c * 2 * (lv + 1) * N;
   const ModQ m = tb.mods[i];
   const uint64_t qi = (uint64_t)m.q;
-  double areg[PER];
   // a, sampled in the coefficient domain
-  for (int k = threadIdx.x; k < N; k += T) s[k] = reduce(sample_uniform_res(seed, kStreamEncA | (uint64_t)i, k, qi), m);
-  __syncthreads();
-  ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)i * N, m);
+  ntt_fwd<LOGN>(s, [&](int j) { return sample_uniform_res(seed, kStreamEncA | (uint64_t)i, j, qi); },
+                tb.fwd_tw + (size_t)i * N, m);
   double* c0 = ct + (size_t)i * N;
   double* c1 = ct + (size_t)(lv + 1 + i) * N;
+  double areg[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int t = threadIdx.x + u * T;
-    areg[u] = s[tb.perm[t]];
+    areg[u] = s[lds_pad(tb.perm[t])];
     c1[t] = areg[u];
   }
-  __syncthreads();
   const double t32 = tb.two32[i];
-  for (int k = threadIdx.x; k < N; k += T)
-    s[k] = reduce(i64_to_res(msg[k], m, t32) + (double)sample_cbd21(seed, kStreamEncE, (uint64_t)k), m);
-  __syncthreads();
-  ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)i * N, m);
+  ntt_fwd<LOGN>(s, [&](int j) {
+      return reduce(i64_to_res(mc[j], m, t32) + (double)sample_cbd21(seed, kStreamEncE, (uint64_t)j), m);
+    }, tb.fwd_tw + (size_t)i * N, m);
   const double* sk_i = sk + (size_t)i * N;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int t = threadIdx.x + u * T;
-    c0[t] = reduce(s[tb.perm[t]] - mulmod(areg[u], sk_i[t], m), m);
+    c0[t] = reduce(s[lds_pad(tb.perm[t])] - mulmod(areg[u], sk_i[t], m), m);
   }
 }
 
@@ -180,35 +124,36 @@ template <int LOGN>
 NTT_KERNEL(LOGN) void k_decrypt_u64(const double* __restrict__ ct, const double* __restrict__ sk, int lv,
                                      uint64_t* __restrict__ out, DevTabs tb) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
+  NTT_LDS(LOGN);
   const int i = blockIdx.x;
   const ModQ m = tb.mods[i];
   const double* c0 = ct + (size_t)i * N;
   const double* c1 = ct + (size_t)(lv + 1 + i) * N;
   const double* sk_i = sk + (size_t)i * N;
-  for (int t = threadIdx.x; t < N; t += T) s[tb.perm[t]] = reduce(c0[t] + mulmod(c1[t], sk_i[t], m), m);
+  for (int t = threadIdx.x; t < N; t += T) s[lds_pad(tb.perm[t])] = reduce(c0[t] + mulmod(c1[t], sk_i[t], m), m);
   __syncthreads();
-  ntt_inv_lds<LOGN>(s, tb.inv_tw + (size_t)i * N, m, tb.ninv[i]);
-  for (int k = threadIdx.x; k < N; k += T) out[(size_t)i * N + k] = f64_to_u64(canon(s[k], m));
+  uint64_t* dst = out + (size_t)i * N;
+  ntt_inv<LOGN>(s, [&](int j, double v) { dst[j] = f64_to_u64(canon(v, m)); }, tb.inv_tw + (size_t)i * N, m,
+                tb.ninv[i]);
 }
 
-// c0 + c1 s -> centred coefficient residues (binary64), for the CRT decoder
+// c0 + c1 s -> canonical coefficient residues (binary64), for the CRT decoder;
+// block (c, i) = ciphertext c, limb i
 template <int LOGN>
-NTT_KERNEL(LOGN) void k_decrypt_f64(const double* __restrict__ ct, const double* __restrict__ sk, int lv,
-                                     double* __restrict__ out, DevTabs tb) {
+NTT_KERNEL(LOGN) void k_decrypt_f64(const double* __restrict__ ct, const double* const* __restrict__ ct_tab,
+                                     const double* __restrict__ sk, int lv, double* __restrict__ out, DevTabs tb) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
+  NTT_LDS(LOGN);
   const int i = blockIdx.x % (lv + 1), c = blockIdx.x / (lv + 1);
   const ModQ m = tb.mods[i];
-  const double* base = ct + (size_t)c * 2 * (lv + 1) * N;
+  const double* base = ct_tab ? ct_tab[c] : ct + (size_t)c * 2 * (lv + 1) * N;
   const double* c0 = base + (size_t)i * N;
   const double* c1 = base + (size_t)(lv + 1 + i) * N;
   const double* sk_i = sk + (size_t)i * N;
-  for (int t = threadIdx.x; t < N; t += T) s[tb.perm[t]] = reduce(c0[t] + mulmod(c1[t], sk_i[t], m), m);
+  for (int t = threadIdx.x; t < N; t += T) s[lds_pad(tb.perm[t])] = reduce(c0[t] + mulmod(c1[t], sk_i[t], m), m);
   __syncthreads();
-  ntt_inv_lds<LOGN>(s, tb.inv_tw + (size_t)i * N, m, tb.ninv[i]);
   double* dst = out + ((size_t)c * (lv + 1) + i) * N;
-  for (int k = threadIdx.x; k < N; k += T) dst[k] = canon(s[k], m);
+  ntt_inv<LOGN>(s, [&](int j, double v) { dst[j] = canon(v, m); }, tb.inv_tw + (size_t)i * N, m, tb.ninv[i]);
 }
 
 // Rotation (Galois) keys.  Block = (key kk, digit j, limb r of Q_L u P):
@@ -220,7 +165,7 @@ NTT_KERNEL(LOGN) void k_rotkey_gen(const double* __restrict__ sk, const int* __r
                                     const uint32_t* __restrict__ galois_of_key, uint64_t seed, RotKeyArgs ka,
                                     double* __restrict__ keys, DevTabs tb) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PER = N / T;
-  __shared__ double s[N];
+  NTT_LDS(LOGN);
   const int nlimb = ka.n_limbs;
   const int r = blockIdx.x % nlimb;
   const int j = (blockIdx.x / nlimb) % ka.beta;
@@ -230,22 +175,17 @@ NTT_KERNEL(LOGN) void k_rotkey_gen(const double* __restrict__ sk, const int* __r
   const int rot = rot_of_key[kk];
   const uint64_t sa = kStreamKeyA | ((uint64_t)j << 40) | ((uint64_t)r << 24) | g;
   const uint64_t se = kStreamKeyE | ((uint64_t)j << 40) | g;
-  double areg[PER];
-  for (int k = threadIdx.x; k < N; k += T) s[k] = reduce(sample_uniform_res(seed, sa, k, (uint64_t)m.q), m);
-  __syncthreads();
-  ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)r * N, m);
+  ntt_fwd<LOGN>(s, [&](int k) { return sample_uniform_res(seed, sa, k, (uint64_t)m.q); }, tb.fwd_tw + (size_t)r * N, m);
   double* kb = keys + ((((size_t)kk * ka.beta + j) * 2 + 0) * nlimb + r) * N;
   double* kaout = keys + ((((size_t)kk * ka.beta + j) * 2 + 1) * nlimb + r) * N;
+  double areg[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int t = threadIdx.x + u * T;
-    areg[u] = s[tb.perm[t]];
+    areg[u] = s[lds_pad(tb.perm[t])];
     kaout[t] = areg[u];
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k < N; k += T) s[k] = (double)sample_cbd21(seed, se, (uint64_t)k);
-  __syncthreads();
-  ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)r * N, m);
+  ntt_fwd<LOGN>(s, [&](int k) { return (double)sample_cbd21(seed, se, (uint64_t)k); }, tb.fwd_tw + (size_t)r * N, m);
   const double* sk_r = sk + (size_t)r * N;
   const bool in_digit = (r < ka.n_q) && (r / ka.alpha == j);
   const double pmod = ka.P_mod[r];
@@ -253,54 +193,61 @@ NTT_KERNEL(LOGN) void k_rotkey_gen(const double* __restrict__ sk, const int* __r
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int t = threadIdx.x + u * T;
-    double v = s[tb.perm[t]] - mulmod(areg[u], sk_r[t], m);
+    double v = s[lds_pad(tb.perm[t])] - mulmod(areg[u], sk_r[t], m);
     if (in_digit) v += mulmod(pmod, sk_r[orbit_shift(t, rot, half)], m);
     kb[t] = reduce(v, m);
   }
 }
 
 // ---------------------------------------------------------------------------
-// ModUp (hoisted once per input ciphertext).
+// ModUp (hoisted once per input ciphertext).  Input ciphertext c of a batch
+// is at ct + c*ct_stride; its digits go to digits + c*dig_stride.
 // step 1: INTT of every limb of c1; y_i = [x_i * (Q_j/q_i)^-1]_{q_i} (canonical)
 // step 2: per (digit j, target limb r not in D_j):
 //         Conv = sum_{i in D_j} y_i [Q_j/q_i]_r  -> NTT -> digits[j][r]
 // ---------------------------------------------------------------------------
 template <int LOGN>
-NTT_KERNEL(LOGN) void k_modup_intt(const double* __restrict__ c1, int lv, const KsLevel* __restrict__ kl,
-                                    double* __restrict__ y, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
-  const int i = blockIdx.x;
+NTT_KERNEL(LOGN) void k_modup_intt(const double* __restrict__ ct, const double* const* __restrict__ ct_tab,
+                                    size_t ct_stride, int lv, const KsLevel* __restrict__ kl, double* __restrict__ y,
+                                    DevTabs tb) {
+  constexpr int N = 1 << LOGN;
+  NTT_LDS(LOGN);
+  const int i = blockIdx.x % (lv + 1), c = blockIdx.x / (lv + 1);
   const ModQ m = tb.mods[i];
-  load_orbit<LOGN>(s, c1 + (size_t)i * N, tb.perm, m);
-  ntt_inv_lds<LOGN>(s, tb.inv_tw + (size_t)i * N, m, tb.ninv[i]);
+  const double* c1 = (ct_tab ? ct_tab[c] : ct + (size_t)c * ct_stride) + (size_t)(lv + 1) * N;
+  lds_from_orbit<LOGN>(s, c1 + (size_t)i * N, tb.perm, m);
   const double ih = kl->up_inv_hat[i];
-  for (int k = threadIdx.x; k < N; k += T) y[(size_t)i * N + k] = canon(mulmod(canon(s[k], m), ih, m), m);
+  double* dst = y + ((size_t)c * (lv + 1) + i) * N;
+  ntt_inv<LOGN>(s, [&](int j, double v) { dst[j] = canon(mulmod(canon(v, m), ih, m), m); }, tb.inv_tw + (size_t)i * N,
+                m, tb.ninv[i]);
 }
 
 template <int LOGN>
-NTT_KERNEL(LOGN) void k_modup_conv(const double* __restrict__ y, const double* __restrict__ c1,
-                                    const KsLevel* __restrict__ kl, double* __restrict__ digits, DevTabs tb) {
+NTT_KERNEL(LOGN) void k_modup_conv(const double* __restrict__ y, const double* __restrict__ ct,
+                                    const double* const* __restrict__ ct_tab, size_t ct_stride,
+                                    const KsLevel* __restrict__ kl, double* __restrict__ digits, size_t dig_stride,
+                                    DevTabs tb) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
-  const KsTask task = kl->up_task[blockIdx.x];
-  const int K = kl->K;
+  NTT_LDS(LOGN);
+  const int nt = kl->n_tasks;
+  const KsTask task = kl->up_task[blockIdx.x % nt];
+  const int c = blockIdx.x / nt;
+  const int K = kl->K, lv = kl->lv;
   const int pi = task.prime;
   const ModQ m = tb.mods[pi];
-  double* dst = digits + ((size_t)task.digit * K + task.limb) * N;
+  double* dst = digits + (size_t)c * dig_stride + ((size_t)task.digit * K + task.limb) * N;
   if (task.nsrc == 0) {  // limb of the digit itself: residues kept as they are
-    const double* src = c1 + (size_t)task.limb * N;
+    const double* src = (ct_tab ? ct_tab[c] : ct + (size_t)c * ct_stride) + (size_t)(lv + 1 + task.limb) * N;
     for (int t = threadIdx.x; t < N; t += T) dst[t] = src[t];
     return;
   }
-  for (int k = threadIdx.x; k < N; k += T) {
-    double acc = 0.0;
-    for (int u = 0; u < task.nsrc; ++u) acc += mulmod(y[(size_t)(task.src0 + u) * N + k], task.hat[u], m);
-    s[k] = reduce(acc, m);
-  }
-  __syncthreads();
-  ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)pi * N, m);
-  store_orbit<LOGN>(s, dst, tb.perm, m);
+  const double* yc = y + (size_t)c * (lv + 1) * N;
+  ntt_fwd<LOGN>(s, [&](int j) {
+      double acc = 0.0;
+      for (int u = 0; u < task.nsrc; ++u) acc += mulmod(yc[(size_t)(task.src0 + u) * N + j], task.hat[u], m);
+      return reduce(acc, m);
+    }, tb.fwd_tw + (size_t)pi * N, m);
+  store_orbit<LOGN>(s, dst, tb.perm);
 }
 
 // ---------------------------------------------------------------------------
@@ -313,40 +260,40 @@ NTT_KERNEL(LOGN) void k_modup_conv(const double* __restrict__ y, const double* _
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_moddown_p(const double* __restrict__ u, const KsLevel* __restrict__ kl,
                                    double* __restrict__ y, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
+  constexpr int N = 1 << LOGN;
+  NTT_LDS(LOGN);
   const int alpha = kl->alpha, K = kl->K, lv = kl->lv;
   const int k = blockIdx.x % alpha, x = blockIdx.x / alpha;
   const int pi = kl->n_q_total + k;
   const ModQ m = tb.mods[pi];
-  load_orbit<LOGN>(s, u + ((size_t)x * K + lv + 1 + k) * N, tb.perm, m);
-  ntt_inv_lds<LOGN>(s, tb.inv_tw + (size_t)pi * N, m, tb.ninv[pi]);
+  lds_from_orbit<LOGN>(s, u + ((size_t)x * K + lv + 1 + k) * N, tb.perm, m);
   const double h = kl->down_half[lv + 1 + k];
   const double ih = kl->down_inv_hat[k];
-  for (int c = threadIdx.x; c < N; c += T)
-    y[((size_t)x * alpha + k) * N + c] = canon(mulmod(canon(s[c] + h, m), ih, m), m);
+  double* dst = y + ((size_t)x * alpha + k) * N;
+  ntt_inv<LOGN>(s, [&](int c, double v) { dst[c] = canon(mulmod(canon(v + h, m), ih, m), m); },
+                tb.inv_tw + (size_t)pi * N, m, tb.ninv[pi]);
 }
 
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_moddown_q(const double* __restrict__ u, const double* __restrict__ y,
-                                   const KsLevel* __restrict__ kl, double* __restrict__ out, DevTabs tb) {
+                                   const KsLevel* __restrict__ kl, double* __restrict__ out,
+                                   double* const* __restrict__ out_tab, DevTabs tb) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
+  NTT_LDS(LOGN);
   const int alpha = kl->alpha, K = kl->K, lv = kl->lv;
   const int i = blockIdx.x % (lv + 1), x = blockIdx.x / (lv + 1);
   const ModQ m = tb.mods[i];
   const double h = kl->down_half[i];
-  for (int c = threadIdx.x; c < N; c += T) {
-    double acc = -h;
-    for (int k = 0; k < alpha; ++k) acc += mulmod(y[((size_t)x * alpha + k) * N + c], kl->down_hat[k * kMaxLimbs + i], m);
-    s[c] = reduce(acc, m);
-  }
-  __syncthreads();
-  ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)i * N, m);
+  const double* yx = y + (size_t)x * alpha * N;
+  ntt_fwd<LOGN>(s, [&](int c) {
+      double acc = -h;
+      for (int k = 0; k < alpha; ++k) acc += mulmod(yx[(size_t)k * N + c], kl->down_hat[k * kMaxLimbs + i], m);
+      return reduce(acc, m);
+    }, tb.fwd_tw + (size_t)i * N, m);
   const double pinv = kl->down_pinv[i];
   const double* ui = u + ((size_t)x * K + i) * N;
-  double* oi = out + ((size_t)x * (lv + 1) + i) * N;
-  for (int t = threadIdx.x; t < N; t += T) oi[t] = reduce(mulmod(ui[t] - s[tb.perm[t]], pinv, m), m);
+  double* oi = out_tab ? out_tab[x >> 1] + ((size_t)(x & 1) * (lv + 1) + i) * N : out + ((size_t)x * (lv + 1) + i) * N;
+  for (int t = threadIdx.x; t < N; t += T) oi[t] = reduce(mulmod(ui[t] - s[lds_pad(tb.perm[t])], pinv, m), m);
 }
 
 // Rescale by q_lv (drop the last limb, coefficient-wise rounding) on `npoly`
@@ -355,25 +302,23 @@ template <int LOGN>
 NTT_KERNEL(LOGN) void k_rescale(const double* __restrict__ in, int lv, const RescaleArgs ra, double* __restrict__ out,
                                  DevTabs tb) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  __shared__ double s[N];
+  NTT_LDS(LOGN);
   const int i = blockIdx.x % lv, x = blockIdx.x / lv;
   const ModQ ml = tb.mods[lv];
   const ModQ m = tb.mods[i];
   // INTT of the dropped limb (every block recomputes it; the limb is L2-resident)
-  load_orbit<LOGN>(s, in + ((size_t)x * (lv + 1) + lv) * N, tb.perm, ml);
-  ntt_inv_lds<LOGN>(s, tb.inv_tw + (size_t)lv * N, ml, tb.ninv[lv]);
-  const double hl = ra.half_mod_last;
-  const double hi = ra.half_mod[i];
-  for (int c = threadIdx.x; c < N; c += T) {
-    const double v = canon(s[c] + hl, ml);  // [c + h]_{q_l}, then conversion to q_i is the identity lift
-    s[c] = reduce(v - hi, m);
-  }
-  __syncthreads();
-  ntt_fwd_lds<LOGN>(s, tb.fwd_tw + (size_t)i * N, m);
+  lds_from_orbit<LOGN>(s, in + ((size_t)x * (lv + 1) + lv) * N, tb.perm, ml);
+  double c[16];
+  ntt_inv_regs<LOGN>(s, c, tb.inv_tw + (size_t)lv * N, ml, tb.ninv[lv]);
+  const double hl = ra.half_mod_last, hi = ra.half_mod[i];
+  // [c + h]_{q_l} lifted to q_i, minus h mod q_i
+#pragma unroll
+  for (int w = 0; w < 16; ++w) c[w] = reduce(canon(c[w] + hl, ml) - hi, m);
+  ntt_fwd_regs<LOGN>(s, c, tb.fwd_tw + (size_t)i * N, m);
   const double inv = ra.inv_last[i];
   const double* ui = in + ((size_t)x * (lv + 1) + i) * N;
   double* oi = out + ((size_t)x * lv + i) * N;
-  for (int t = threadIdx.x; t < N; t += T) oi[t] = reduce(mulmod(ui[t] - s[tb.perm[t]], inv, m), m);
+  for (int t = threadIdx.x; t < N; t += T) oi[t] = reduce(mulmod(ui[t] - s[lds_pad(tb.perm[t])], inv, m), m);
 }
 
 // ---------------------------------------------------------------------------
@@ -443,13 +388,16 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 }
 
 // P * (c0, c1) on the Q limbs, [2][lv+1][N]
-__global__ __launch_bounds__(256) void k_scale_by_p(const double* __restrict__ ct, int lv, int N, const double* __restrict__ pmod,
+__global__ __launch_bounds__(256) void k_scale_by_p(const double* __restrict__ ct, const double* const* __restrict__ ct_tab,
+                                                    int lv, int N, const double* __restrict__ pmod,
                                                     const ModQ* __restrict__ mods, double* __restrict__ out) {
   const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
   const size_t tot = (size_t)2 * (lv + 1) * N;
   if (idx >= tot) return;
+  const int c = blockIdx.y;
+  const double* src = ct_tab ? ct_tab[c] : ct + (size_t)c * tot;
   const int i = (int)((idx / N) % (lv + 1));
-  out[idx] = reduce(mulmod(ct[idx], pmod[i], mods[i]), mods[i]);
+  out[(size_t)c * tot + idx] = reduce(mulmod(src[idx], pmod[i], mods[i]), mods[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -602,11 +550,15 @@ hipError_t launch_keygen(const LaunchCtx& L, uint64_t seed, double* sk, int n_mo
 }
 
 template <int LOGN>
-static void encrypt_impl(const LaunchCtx& L, const int64_t* msg, const double* sk, uint64_t seed, int lv, double* ct) {
-  hipLaunchKernelGGL(k_encrypt<LOGN>, dim3(lv + 1), dim3(NttShape<LOGN>::T), 0, L.stream, msg, sk, seed, lv, ct, L.tb);
+static void encrypt_impl(const LaunchCtx& L, const int64_t* msg, int nct, const double* sk, uint64_t seed, int lv,
+                         double* ct, double* const* ct_tab) {
+  hipLaunchKernelGGL(k_encrypt<LOGN>, dim3(nct * (lv + 1)), dim3(NttShape<LOGN>::T), 0, L.stream, msg, sk, seed, lv, ct,
+                     ct_tab, L.tb);
 }
-hipError_t launch_encrypt(const LaunchCtx& L, const int64_t* msg, const double* sk, uint64_t seed, int lv, double* ct) {
-  DISPATCH_LOGN(L, encrypt_impl, L, msg, sk, seed, lv, ct);
+hipError_t launch_encrypt(const LaunchCtx& L, const int64_t* msg, int nct, const double* sk, uint64_t seed, int lv,
+                          double* ct, double* const* ct_tab) {
+  if (nct <= 0) return hipSuccess;
+  DISPATCH_LOGN(L, encrypt_impl, L, msg, nct, sk, seed, lv, ct, ct_tab);
   return hipGetLastError();
 }
 
@@ -620,11 +572,14 @@ hipError_t launch_decrypt_u64(const LaunchCtx& L, const double* ct, const double
 }
 
 template <int LOGN>
-static void decrypt_f64_impl(const LaunchCtx& L, const double* ct, int nct, const double* sk, int lv, double* out) {
-  hipLaunchKernelGGL(k_decrypt_f64<LOGN>, dim3(nct * (lv + 1)), dim3(NttShape<LOGN>::T), 0, L.stream, ct, sk, lv, out, L.tb);
+static void decrypt_f64_impl(const LaunchCtx& L, const double* ct, const double* const* ct_tab, int nct, const double* sk,
+                             int lv, double* out) {
+  hipLaunchKernelGGL(k_decrypt_f64<LOGN>, dim3(nct * (lv + 1)), dim3(NttShape<LOGN>::T), 0, L.stream, ct, ct_tab, sk, lv,
+                     out, L.tb);
 }
-hipError_t launch_decrypt_f64(const LaunchCtx& L, const double* ct, int nct, const double* sk, int lv, double* out) {
-  DISPATCH_LOGN(L, decrypt_f64_impl, L, ct, nct, sk, lv, out);
+hipError_t launch_decrypt_f64(const LaunchCtx& L, const double* ct, int nct, const double* sk, int lv, double* out,
+                              const double* const* ct_tab) {
+  DISPATCH_LOGN(L, decrypt_f64_impl, L, ct, ct_tab, nct, sk, lv, out);
   return hipGetLastError();
 }
 
@@ -642,26 +597,30 @@ hipError_t launch_rotkey_gen(const LaunchCtx& L, const double* sk, const int* ro
 }
 
 template <int LOGN>
-static void modup_impl(const LaunchCtx& L, const double* c1, int lv, const KsLevel* kl_dev, int n_tasks, double* y,
-                       double* digits) {
-  hipLaunchKernelGGL(k_modup_intt<LOGN>, dim3(lv + 1), dim3(NttShape<LOGN>::T), 0, L.stream, c1, lv, kl_dev, y, L.tb);
-  hipLaunchKernelGGL(k_modup_conv<LOGN>, dim3(n_tasks), dim3(NttShape<LOGN>::T), 0, L.stream, y, c1, kl_dev, digits, L.tb);
+static void modup_impl(const LaunchCtx& L, const double* ct, const double* const* ct_tab, size_t ct_stride, int nct,
+                       int lv, const KsLevel* kl_dev, int n_tasks, double* y, double* digits, size_t dig_stride) {
+  hipLaunchKernelGGL(k_modup_intt<LOGN>, dim3(nct * (lv + 1)), dim3(NttShape<LOGN>::T), 0, L.stream, ct, ct_tab, ct_stride,
+                     lv, kl_dev, y, L.tb);
+  hipLaunchKernelGGL(k_modup_conv<LOGN>, dim3(nct * n_tasks), dim3(NttShape<LOGN>::T), 0, L.stream, y, ct, ct_tab,
+                     ct_stride, kl_dev, digits, dig_stride, L.tb);
 }
-hipError_t launch_modup(const LaunchCtx& L, const double* c1, int lv, const KsLevel* kl_dev, int n_tasks, double* y,
-                        double* digits) {
-  DISPATCH_LOGN(L, modup_impl, L, c1, lv, kl_dev, n_tasks, y, digits);
+hipError_t launch_modup(const LaunchCtx& L, const double* ct, size_t ct_stride, int nct, int lv, const KsLevel* kl_dev,
+                        int n_tasks, double* y, double* digits, size_t dig_stride, const double* const* ct_tab) {
+  if (nct <= 0) return hipSuccess;
+  DISPATCH_LOGN(L, modup_impl, L, ct, ct_tab, ct_stride, nct, lv, kl_dev, n_tasks, y, digits, dig_stride);
   return hipGetLastError();
 }
 
 template <int LOGN>
 static void moddown_impl(const LaunchCtx& L, const double* u, int npoly, int lv, int alpha, const KsLevel* kl_dev,
-                         double* y, double* out) {
+                         double* y, double* out, double* const* out_tab) {
   hipLaunchKernelGGL(k_moddown_p<LOGN>, dim3(npoly * alpha), dim3(NttShape<LOGN>::T), 0, L.stream, u, kl_dev, y, L.tb);
-  hipLaunchKernelGGL(k_moddown_q<LOGN>, dim3(npoly * (lv + 1)), dim3(NttShape<LOGN>::T), 0, L.stream, u, y, kl_dev, out, L.tb);
+  hipLaunchKernelGGL(k_moddown_q<LOGN>, dim3(npoly * (lv + 1)), dim3(NttShape<LOGN>::T), 0, L.stream, u, y, kl_dev, out,
+                     out_tab, L.tb);
 }
 hipError_t launch_moddown(const LaunchCtx& L, const double* u, int npoly, int lv, int alpha, const KsLevel* kl_dev,
-                          double* y, double* out) {
-  DISPATCH_LOGN(L, moddown_impl, L, u, npoly, lv, alpha, kl_dev, y, out);
+                          double* y, double* out, double* const* out_tab) {
+  DISPATCH_LOGN(L, moddown_impl, L, u, npoly, lv, alpha, kl_dev, y, out, out_tab);
   return hipGetLastError();
 }
 
@@ -717,9 +676,11 @@ hipError_t launch_eager_term(const LaunchCtx& L, const double* c0, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_scale_by_p(const LaunchCtx& L, const double* ct, int lv, int N, const double* pmod_dev, double* out) {
+hipError_t launch_scale_by_p(const LaunchCtx& L, const double* ct, int lv, int N, const double* pmod_dev, double* out,
+                             int nct, const double* const* ct_tab) {
   const size_t tot = (size_t)2 * (lv + 1) * N;
-  hipLaunchKernelGGL(k_scale_by_p, dim3(blocks_for(tot)), dim3(256), 0, L.stream, ct, lv, N, pmod_dev, L.tb.mods, out);
+  hipLaunchKernelGGL(k_scale_by_p, dim3(blocks_for(tot), nct), dim3(256), 0, L.stream, ct, ct_tab, lv, N, pmod_dev,
+                     L.tb.mods, out);
   return hipGetLastError();
 }
 

@@ -78,15 +78,22 @@ struct DiagArgs {
 
 hipError_t launch_ntt(const LaunchCtx& L, NttOp op, const void* in, void* out, int nblocks, LimbMap map);
 hipError_t launch_keygen(const LaunchCtx& L, uint64_t seed, double* sk, int n_mod);
-hipError_t launch_encrypt(const LaunchCtx& L, const int64_t* msg, const double* sk, uint64_t seed, int lv, double* ct);
+// nct ciphertexts [nct][2][lv+1][N] from messages [nct][N]; ciphertext c uses seed + c
+hipError_t launch_encrypt(const LaunchCtx& L, const int64_t* msg, int nct, const double* sk, uint64_t seed, int lv,
+                          double* ct, double* const* ct_tab = nullptr);
 hipError_t launch_decrypt_u64(const LaunchCtx& L, const double* ct, const double* sk, int lv, uint64_t* out);
-hipError_t launch_decrypt_f64(const LaunchCtx& L, const double* ct, int nct, const double* sk, int lv, double* out);
+hipError_t launch_decrypt_f64(const LaunchCtx& L, const double* ct, int nct, const double* sk, int lv, double* out,
+                              const double* const* ct_tab = nullptr);
 hipError_t launch_rotkey_gen(const LaunchCtx& L, const double* sk, const int* rot_of_key, const uint32_t* gal, int nkeys,
                              uint64_t seed, const RotKeyArgs& ka, double* keys);
-hipError_t launch_modup(const LaunchCtx& L, const double* c1, int lv, const KsLevel* kl_dev, int n_tasks, double* y,
-                        double* digits);
+// ModUp of the c1 halves of nct ciphertexts (ct + c*ct_stride); y holds
+// [nct][lv+1][N] coefficient scratch; digits of ciphertext c at digits + c*dig_stride
+hipError_t launch_modup(const LaunchCtx& L, const double* ct, size_t ct_stride, int nct, int lv, const KsLevel* kl_dev,
+                        int n_tasks, double* y, double* digits, size_t dig_stride,
+                        const double* const* ct_tab = nullptr);
+// out_tab (optional): output of poly x at out_tab[x/2] + (x%2)*(lv+1)*N
 hipError_t launch_moddown(const LaunchCtx& L, const double* u, int npoly, int lv, int alpha, const KsLevel* kl_dev,
-                          double* y, double* out);
+                          double* y, double* out, double* const* out_tab = nullptr);
 hipError_t launch_rescale(const LaunchCtx& L, const double* in, int npoly, int lv, const RescaleArgs& ra, double* out);
 hipError_t launch_diag_lazy(const LaunchCtx& L, const DiagArgs& a, int nchunk);
 hipError_t launch_sum_partials(const LaunchCtx& L, const double* part, int nchunk, int K, int N, LimbMap limb_prime,
@@ -100,7 +107,8 @@ hipError_t launch_add_limbs(const LaunchCtx& L, const double* a, const double* b
 // acc (ct at lv) += (c0[shift rot] + v0, v1) * pt   (v0 = v1 = null: (c0, c1) unshifted)
 hipError_t launch_eager_term(const LaunchCtx& L, const double* c0, const double* c1, const double* v, int rot, const double* pt,
                              int lv, int N, double* acc);
-hipError_t launch_scale_by_p(const LaunchCtx& L, const double* ct, int lv, int N, const double* pmod_dev, double* out);
+hipError_t launch_scale_by_p(const LaunchCtx& L, const double* ct, int lv, int N, const double* pmod_dev, double* out,
+                             int nct = 1, const double* const* ct_tab = nullptr);
 hipError_t launch_ct_mul_pt(const LaunchCtx& L, const double* ct, const double* pt, int lv, int N, double* out);
 hipError_t launch_ct_add(const LaunchCtx& L, const double* a, const double* b, int lv, int N, double* out);
 hipError_t launch_automorph(const LaunchCtx& L, const double* in, int npoly_limbs, int N, int rot, double* out);

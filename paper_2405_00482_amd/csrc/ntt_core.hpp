@@ -1,18 +1,24 @@
 // Negacyclic NTT over binary64-held residues, one ring limb per workgroup,
-// the whole limb resident in LDS (N <= 2^14: 128 KiB of the 160 KiB per CU).
+// the whole limb resident in LDS (N <= 2^14: 136 KiB of the 160 KiB per CU).
 //
 // Evaluation-domain ("NTT domain") ORDER.  Index t of a transformed limb holds
 // a(psi^e(t)) with e(t) = 5^t mod 2N for t < N/2 and e(t) = -5^(t-N/2) mod 2N
 // for t >= N/2.  The automorphism X -> X^(5^i) then maps index t to the index
 // (t + i) mod N/2 within the same half, so a slot rotation is a cyclic shift of
-// contiguous memory instead of a scattered gather.  The butterflies themselves
-// run in the textbook bit-reversed order (Cooley-Tukey forward, Gentleman-Sande
-// inverse, psi-twist merged into the twiddles); a fixed permutation between
-// the bit-reversed index and t is applied when the limb leaves or enters LDS.
+// contiguous memory instead of a scattered gather.  The butterflies run in the
+// textbook bit-reversed order (Cooley-Tukey forward, Gentleman-Sande inverse,
+// psi-twist merged into the twiddles); a fixed permutation between the
+// bit-reversed index and t is applied when the limb leaves or enters LDS.
 //
-// Value ranges: inputs may be any integers with |x| < 2^51; butterfly outputs
-// are re-centred every few stages so that every mulmod sees |a| <= 4q; outputs
-// are centred (|x| <= (q+1)/2).
+// Schedule.  N/16 threads each hold 16 elements in registers; up to four
+// radix-2 stages run on them between two LDS exchanges ("passes"), so a 2^14
+// transform makes four LDS round trips instead of fourteen.  The LDS array is
+// padded by one double every 16 (lds_pad) so that the strided set loads of
+// every pass are close to bank-conflict free.
+//
+// Value ranges: inputs may be any integers with |x| < 2^51; values are
+// re-centred at the end of every pass (forward) or every second stage
+// (inverse), so every mulmod sees |a| <= 4q; outputs are centred.
 #pragma once
 #include "fp64_mod.hpp"
 
@@ -31,68 +37,210 @@ struct DevTabs {
 template <int LOGN>
 struct NttShape {
   static constexpr int N = 1 << LOGN;
-  static constexpr int T = N / 16;        // threads per workgroup
-  static constexpr int BF = N / 2 / T;    // butterflies per thread per stage (8)
+  static constexpr int T = N / 16;              // threads per workgroup
+  static constexpr int LDS = N + N / 16;        // padded LDS doubles
+  static constexpr int S0 = LOGN - 12;          // stages of the leading (large-span) pass
 };
 
-// forward transform of s[0..N) in place: natural coefficient order in,
-// bit-reversed evaluation order out (centred).
-template <int LOGN>
-__device__ __forceinline__ void ntt_fwd_lds(double* s, const double* __restrict__ tw, ModQ m) {
-  constexpr int T = NttShape<LOGN>::T;
-  constexpr int BF = NttShape<LOGN>::BF;
-  const int tid = threadIdx.x;
-#pragma unroll 1
-  for (int lg = 0; lg < LOGN; ++lg) {
-    const int lt = LOGN - 1 - lg;          // log2 of the butterfly span t
-    const int t = 1 << lt;
-    const bool red = ((lg & 3) == 3) || (lg == LOGN - 1);
+__device__ __forceinline__ int lds_pad(int j) { return j + (j >> 4); }
+
+// S radix-2 Cooley-Tukey stages lg0 .. lg0+S-1 on register sets.  Each thread
+// owns 16 / 2^S sets of 2^S elements {base + u * stride}, stride = span of the
+// last stage of the pass.  A set lies inside one butterfly group of stage lg0
+// (group g0 = base >> (LOGN - lg0)); at stage lg0 + st it spans 2^st groups
+// g0 * 2^st + k, whose twiddles are contiguous in the table, so a pass reads
+// 2^S - 1 twiddles per set.
+template <int LOGN, int S>
+__device__ __forceinline__ void ct_pass_regs(double (&x)[16], int lg0, const int (&base)[16 >> S], int /*stride*/,
+                                             const double* __restrict__ tw, ModQ m) {
+  constexpr int SET = 1 << S;
 #pragma unroll
-    for (int r = 0; r < BF; ++r) {
-      const int b = tid + r * T;
-      const int i = b >> lt;
-      const int j = (i << (lt + 1)) + (b & (t - 1));
-      const double S = tw[(1 << lg) + i];
-      const double U = s[j];
-      const double V = mulmod(s[j + t], S, m);
-      double x = U + V, y = U - V;
-      if (red) { x = reduce(x, m); y = reduce(y, m); }
-      s[j] = x;
-      s[j + t] = y;
+  for (int q = 0; q < (16 >> S); ++q) {
+    const int g0 = base[q] >> (LOGN - lg0);
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      const int half = SET >> (st + 1);
+      double w[1 << (S > 0 ? S - 1 : 0)];
+      const double* tws = tw + (1 << (lg0 + st)) + (g0 << st);
+#pragma unroll
+      for (int k = 0; k < (1 << st); ++k) w[k] = tws[k];
+#pragma unroll
+      for (int u = 0; u < SET; ++u) {
+        if (u & half) continue;
+        const double U = x[q * SET + u];
+        const double V = mulmod(x[q * SET + u + half], w[u >> (S - st)], m);
+        x[q * SET + u] = U + V;
+        x[q * SET + u + half] = U - V;
+      }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = reduce(x[k], m);
+}
+
+// set bases of a pass: set c = q*T + tid, blocks of SET*stride elements
+template <int LOGN, int S>
+__device__ __forceinline__ void pass_bases(int (&base)[16 >> S], int stride) {
+  constexpr int T = NttShape<LOGN>::T;
+#pragma unroll
+  for (int q = 0; q < (16 >> S); ++q) {
+    const int c = q * T + (int)threadIdx.x;
+    const int blk = c / stride, off = c % stride;
+    base[q] = blk * (stride << S) + off;
+  }
+}
+
+template <int LOGN, int S>
+__device__ __forceinline__ void lds_load_sets(const double* s, double (&x)[16], const int (&base)[16 >> S], int stride) {
+#pragma unroll
+  for (int q = 0; q < (16 >> S); ++q)
+#pragma unroll
+    for (int u = 0; u < (1 << S); ++u) x[q * (1 << S) + u] = s[lds_pad(base[q] + u * stride)];
+}
+template <int LOGN, int S>
+__device__ __forceinline__ void lds_store_sets(double* s, const double (&x)[16], const int (&base)[16 >> S], int stride) {
+#pragma unroll
+  for (int q = 0; q < (16 >> S); ++q)
+#pragma unroll
+    for (int u = 0; u < (1 << S); ++u) s[lds_pad(base[q] + u * stride)] = x[q * (1 << S) + u];
+}
+
+// Forward transform.  c[w] is coefficient tid + w*T of the thread (natural
+// order, any |x| < 2^51); the first pass runs on these registers directly.
+// The result is left in LDS in bit-reversed order: read it with
+// s[lds_pad(perm[t])] after the call (which ends with a barrier).  The call
+// begins with a barrier, so `s` may still be in use by the caller before it.
+template <int LOGN>
+__device__ __forceinline__ void ntt_fwd_regs(double* s, const double (&c)[16], const double* __restrict__ tw, ModQ m) {
+  constexpr int S0 = NttShape<LOGN>::S0;
+  double x[16];
+  int lg = 0;
+  {
+    constexpr int S = S0 > 0 ? S0 : 4;
+    const int stride = 1 << (LOGN - S);
+    int base[16 >> S];
+    pass_bases<LOGN, S>(base, stride);
+    // register slot (q, u) holds coefficient base[q] + u*stride = tid + T*(q + u*(16>>S))
+#pragma unroll
+    for (int q = 0; q < (16 >> S); ++q)
+#pragma unroll
+      for (int u = 0; u < (1 << S); ++u) x[q * (1 << S) + u] = reduce(c[q + u * (16 >> S)], m);
+    ct_pass_regs<LOGN, S>(x, 0, base, stride, tw, m);
+    __syncthreads();
+    lds_store_sets<LOGN, S>(s, x, base, stride);
+    lg = S;
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (; lg < LOGN; lg += 4) {
+    const int stride = 1 << (LOGN - lg - 4);
+    int base[1];
+    pass_bases<LOGN, 4>(base, stride);
+    lds_load_sets<LOGN, 4>(s, x, base, stride);
+    ct_pass_regs<LOGN, 4>(x, lg, base, stride, tw, m);
+    lds_store_sets<LOGN, 4>(s, x, base, stride);
     __syncthreads();
   }
 }
 
-// inverse transform in place: bit-reversed evaluation order in, natural
-// coefficient order out, scaled by N^-1 and centred.
-template <int LOGN>
-__device__ __forceinline__ void ntt_inv_lds(double* s, const double* __restrict__ itw, ModQ m, double ninv) {
-  constexpr int N = NttShape<LOGN>::N;
+// forward transform of coefficients produced by load(j)
+template <int LOGN, class Load>
+__device__ __forceinline__ void ntt_fwd(double* s, Load load, const double* __restrict__ tw, ModQ m) {
   constexpr int T = NttShape<LOGN>::T;
-  constexpr int BF = NttShape<LOGN>::BF;
-  const int tid = threadIdx.x;
-#pragma unroll 1
-  for (int lg = LOGN - 1; lg >= 0; --lg) {
-    const int lt = LOGN - 1 - lg;
-    const int t = 1 << lt;
-    const bool red = (lt & 1) == 1;
+  double c[16];
 #pragma unroll
-    for (int r = 0; r < BF; ++r) {
-      const int b = tid + r * T;
-      const int i = b >> lt;
-      const int j = (i << (lt + 1)) + (b & (t - 1));
-      const double S = itw[(1 << lg) + i];
-      const double U = s[j];
-      const double V = s[j + t];
-      double x = U + V;
-      if (red) x = reduce(x, m);
-      s[j] = x;
-      s[j + t] = mulmod(U - V, S, m);
+  for (int w = 0; w < 16; ++w) c[w] = load((int)threadIdx.x + w * T);
+  ntt_fwd_regs<LOGN>(s, c, tw, m);
+}
+
+// S Gentleman-Sande stages, lg1, lg1-1, ..., lg1-S+1 (span doubling each
+// stage); sets {base + u * stride}, stride = span of the first stage.  The
+// set is one group of stage lg1-S+1; at stage lg1-st it spans 2^(S-1-st)
+// groups with contiguous twiddles.
+template <int LOGN, int S>
+__device__ __forceinline__ void gs_pass_regs(double (&x)[16], int lg1, const int (&base)[16 >> S], int /*stride*/,
+                                             const double* __restrict__ itw, ModQ m) {
+  constexpr int SET = 1 << S;
+#pragma unroll
+  for (int q = 0; q < (16 >> S); ++q) {
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      const int lg = lg1 - st;
+      const int half = 1 << st;
+      const int gbase = base[q] >> (LOGN - lg);  // group of element u = 0 at this stage
+      double w[1 << (S > 0 ? S - 1 : 0)];
+      const double* tws = itw + (1 << lg) + gbase;
+#pragma unroll
+      for (int k = 0; k < (SET >> (st + 1)); ++k) w[k] = tws[k];
+#pragma unroll
+      for (int u = 0; u < SET; ++u) {
+        if (u & half) continue;
+        const double U = x[q * SET + u];
+        const double V = x[q * SET + u + half];
+        double sum = U + V;
+        if (st & 1) sum = reduce(sum, m);
+        x[q * SET + u] = sum;
+        x[q * SET + u + half] = mulmod(U - V, w[u >> (st + 1)], m);
+      }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = reduce(x[k], m);
+}
+
+// Inverse transform of the bit-reversed data already in LDS (padded, after a
+// barrier).  On return c[w] is coefficient tid + w*T of the natural-order
+// result times N^-1, centred.  LDS is still being read by other threads when
+// this returns: barrier before writing `s` again (ntt_fwd_regs does).
+template <int LOGN>
+__device__ __forceinline__ void ntt_inv_regs(double* s, double (&c)[16], const double* __restrict__ itw, ModQ m,
+                                             double ninv) {
+  constexpr int S0 = NttShape<LOGN>::S0;
+  double x[16];
+  int lg1 = LOGN - 1;
+  constexpr int NFULL = S0 > 0 ? 3 : 2;
+#pragma unroll 1
+  for (int p = 0; p < NFULL; ++p, lg1 -= 4) {
+    const int stride = 1 << (LOGN - 1 - lg1);
+    int base[1];
+    pass_bases<LOGN, 4>(base, stride);
+    lds_load_sets<LOGN, 4>(s, x, base, stride);
+    gs_pass_regs<LOGN, 4>(x, lg1, base, stride, itw, m);
+    lds_store_sets<LOGN, 4>(s, x, base, stride);
     __syncthreads();
   }
-  for (int k = tid; k < N; k += T) s[k] = reduce(mulmod(s[k], ninv, m), m);
+  {
+    constexpr int S = S0 > 0 ? S0 : 4;
+    const int stride = 1 << (LOGN - 1 - lg1);
+    int base[16 >> S];
+    pass_bases<LOGN, S>(base, stride);
+    lds_load_sets<LOGN, S>(s, x, base, stride);
+    gs_pass_regs<LOGN, S>(x, lg1, base, stride, itw, m);
+#pragma unroll
+    for (int q = 0; q < (16 >> S); ++q)
+#pragma unroll
+      for (int u = 0; u < (1 << S); ++u) c[q + u * (16 >> S)] = reduce(mulmod(x[q * (1 << S) + u], ninv, m), m);
+  }
+}
+
+// inverse transform handing coefficient j to store(j, v)
+template <int LOGN, class Store>
+__device__ __forceinline__ void ntt_inv(double* s, Store store, const double* __restrict__ itw, ModQ m, double ninv) {
+  constexpr int T = NttShape<LOGN>::T;
+  double c[16];
+  ntt_inv_regs<LOGN>(s, c, itw, m, ninv);
+#pragma unroll
+  for (int w = 0; w < 16; ++w) store((int)threadIdx.x + w * T, c[w]);
+}
+
+
+// Bring an evaluation-domain limb (orbit order, |x| <= 2^51) into LDS in
+// bit-reversed order for the inverse transform.
+template <int LOGN>
+__device__ __forceinline__ void lds_from_orbit(double* s, const double* __restrict__ in, const uint32_t* __restrict__ perm,
+                                               ModQ m) {
+  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
+  for (int t = threadIdx.x; t < N; t += T) s[lds_pad(perm[t])] = reduce(in[t], m);
   __syncthreads();
 }
 

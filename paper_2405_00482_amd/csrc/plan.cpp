@@ -307,15 +307,31 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
     int z = 0;
     for (int cb = 0; cb < p->info.col_blocks; ++cb) {
       const double* ct = ct_in + (size_t)cb * 2 * Q;
-      if (mprime > 1) HIP_TRY(launch_modup(L, ct + Q, lv, c->ks_dev + lv, kl.n_tasks, yup, digits));
+      if (mprime > 1) {
+        KernelTimer kt(c, stream, PVFL_TIMING_MODUP, 8.0 * (double)(Q + (size_t)p->beta * KN));
+        HIP_TRY(launch_modup(L, ct, 0, 1, lv, c->ks_dev + lv, kl.n_tasks, yup, digits, 0));
+        kt.stop();
+      }
       HIP_TRY(launch_scale_by_p(L, ct, lv, N, c->pmod_dev, pc));
       a.pt = pts + (size_t)(b * p->info.col_blocks + cb) * mprime * KN;
       a.part = part + (size_t)z * 2 * KN;
-      HIP_TRY(launch_diag_lazy(L, a, p->nchunk));
+      {
+        // algorithmic bytes: every key and plaintext limb once, digits and P*c once, partials written
+        const double key_bytes = 8.0 * (double)(mprime - 1) * 2 * p->beta * KN;
+        const double bytes = key_bytes + 8.0 * ((double)mprime * KN + (double)p->beta * KN + 2.0 * Q +
+                                                 (double)p->nchunk * 2 * KN);
+        KernelTimer kt(c, stream, PVFL_TIMING_DIAG, bytes);
+        HIP_TRY(launch_diag_lazy(L, a, p->nchunk));
+        kt.stop();
+      }
       z += p->nchunk;
     }
     HIP_TRY(launch_sum_partials(L, part, z, K, N, lp, acc));
-    HIP_TRY(launch_moddown(L, acc, 2, lv, c->alpha, c->ks_dev + lv, ydown, out + (size_t)b * 2 * Q));
+    {
+      KernelTimer kt(c, stream, PVFL_TIMING_MODDOWN, 8.0 * (double)(2 * KN + 2 * Q));
+      HIP_TRY(launch_moddown(L, acc, 2, lv, c->alpha, c->ks_dev + lv, ydown, out + (size_t)b * 2 * Q));
+      kt.stop();
+    }
   }
   return PVFL_OK;
 }
@@ -338,7 +354,7 @@ static pvfl_status run_diag_eager(const pvfl_plan* p, const double* ct_in, const
     HIP_TRY(launch_fill_zero(L, acc, 2 * Q));
     for (int cb = 0; cb < p->info.col_blocks; ++cb) {
       const double* ct = ct_in + (size_t)cb * 2 * Q;
-      if (mprime > 1) HIP_TRY(launch_modup(L, ct + Q, lv, c->ks_dev + lv, kl.n_tasks, yup, digits));
+      if (mprime > 1) HIP_TRY(launch_modup(L, ct, 0, 1, lv, c->ks_dev + lv, kl.n_tasks, yup, digits, 0));
       for (int i = 0; i < mprime; ++i) {
         const double* pt = pts + ((size_t)(b * p->info.col_blocks + cb) * mprime + i) * Q;
         if (i == 0) {

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpvfl.so")
 
 PLAN_HYBRID, PLAN_DIAG, PLAN_ROW, PLAN_CTMAT = 0, 1, 2, 3
+TIMING_DIAG, TIMING_ENCODE, TIMING_MODUP, TIMING_MODDOWN = 0, 1, 2, 3
 
 _STATUS = {0: "OK", -1: "PVFL_E_INVALID", -2: "PVFL_E_SHAPE", -3: "PVFL_E_LEVEL", -4: "PVFL_E_NOKEY",
            -5: "PVFL_E_NOMEM", -6: "PVFL_E_DEVICE", -7: "PVFL_E_PLAN"}
@@ -38,6 +39,11 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("n_out", ctypes.c_int32),
                 ("level", ctypes.c_int32), ("lazy_moddown", ctypes.c_int32), ("ras_in_ct", ctypes.c_int32),
                 ("pack", ctypes.c_int32), ("pt_log2_scale", ctypes.c_double)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("group", ctypes.c_int32), ("chunk", ctypes.c_int32), ("vec", ctypes.c_int32),
+                ("chunk_major", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -88,6 +94,19 @@ def lib():
             "pvfl_encode_pt": [_VP, _VP, ctypes.c_int64, _VP, _VP],
             "pvfl_encrypt": [_VP, _VP, _VP, ctypes.c_int64, u64, _VP, _VP],
             "pvfl_decrypt_decode": [_VP, _VP, _VP, _VP, _VP],
+            "pvfl_timing_enable": [_VP, i32],
+            "pvfl_batch_create": [_VP, i32, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                  ctypes.POINTER(_VP), _VP, ctypes.POINTER(BatchOpts), ctypes.POINTER(_VP)],
+            "pvfl_batch_encode": [_VP, _VP],
+            "pvfl_batch_encrypt": [_VP, _VP, u64, _VP],
+            "pvfl_batch_matmul": [_VP, _VP],
+            "pvfl_batch_decrypt": [_VP, _VP, _VP],
+            "pvfl_batch_run": [_VP, _VP, u64, i32, _VP],
+            "pvfl_batch_info": [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double)],
+            "pvfl_timing_read": [_VP, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_double)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -97,7 +116,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [_VP]
             f.restype = sz
-        for name in ("pvfl_context_destroy", "pvfl_sk_destroy", "pvfl_rotkeys_destroy", "pvfl_plan_destroy"):
+        for name in ("pvfl_context_destroy", "pvfl_sk_destroy", "pvfl_rotkeys_destroy", "pvfl_plan_destroy",
+                     "pvfl_batch_destroy"):
             f = getattr(L, name)
             f.argtypes = [_VP]
             f.restype = None
@@ -183,6 +203,15 @@ class Context(_Handle):
         _check(lib().pvfl_plan_create(self.h, ctypes.byref(o), ctypes.byref(h)))
         return Plan(h, self)
 
+    def timing_enable(self, on: bool):
+        _check(lib().pvfl_timing_enable(self.h, int(on)))
+
+    def timing_read(self, cls: int):
+        """(total_ms, launches, algorithmic_bytes) of one kernel class; clears it"""
+        ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().pvfl_timing_read(self.h, cls, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+        return ms.value, n.value, by.value
+
     # integer-level entries
     def pt_import(self, level: int, with_p: bool, m_i64, out):
         count = m_i64.shape[0]
@@ -262,3 +291,51 @@ class Plan(_Handle):
         ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
         _check(lib().pvfl_matmul_ct_pt(self.h, _ptr(ct), _ptr(pt), keys.h if keys is not None else None, _ptr(out),
                                        _ptr(ws), ws_bytes, _stream()))
+
+
+def _ptr_array(items):
+    arr = (_VP * len(items))()
+    for i, t in enumerate(items):
+        arr[i] = t.data_ptr() if t is not None else None
+    return arr
+
+
+class Batch(_Handle):
+    """Many independent products run phase by phase in single launches."""
+    _destroy = "pvfl_batch_destroy"
+
+    def __init__(self, ctx: Context, plans, X=None, v=None, pt=None, ct=None, out=None, y=None, keys=None,
+                 group: int = 2, chunk: int = 32, vec: int = 1, chunk_major: bool = True):
+        n = len(plans)
+        plan_arr = (_VP * n)(*[p.h.value for p in plans])
+        ld = (ctypes.c_int64 * n)(*[(x.stride(0) if x is not None and x.dim() == 2 else p.info["n"])
+                                    for x, p in zip(X if X is not None else [None] * n, plans)])
+        h = _VP()
+        _check(lib().pvfl_batch_create(ctx.h, n, plan_arr,
+                                       _ptr_array(X) if X is not None else None, ld,
+                                       _ptr_array(v) if v is not None else None,
+                                       _ptr_array(pt), _ptr_array(ct), _ptr_array(out),
+                                       _ptr_array(y) if y is not None else None,
+                                       keys.h if keys is not None else None,
+                                       ctypes.byref(BatchOpts(group, chunk, vec, int(chunk_major))), ctypes.byref(h)))
+        super().__init__(h, keep=(ctx, plans, X, v, pt, ct, out, y, keys))
+
+    def encode(self):
+        _check(lib().pvfl_batch_encode(self.h, _stream()))
+
+    def encrypt(self, sk, seed: int):
+        _check(lib().pvfl_batch_encrypt(self.h, sk.h, seed, _stream()))
+
+    def matmul(self):
+        _check(lib().pvfl_batch_matmul(self.h, _stream()))
+
+    def decrypt(self, sk):
+        _check(lib().pvfl_batch_decrypt(self.h, sk.h, _stream()))
+
+    def run(self, sk, seed: int, graph: bool = False):
+        _check(lib().pvfl_batch_run(self.h, sk.h, seed, int(graph), _stream()))
+
+    def info(self):
+        n, kb, pb = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().pvfl_batch_info(self.h, ctypes.byref(n), ctypes.byref(kb), ctypes.byref(pb)))
+        return {"work_items": n.value, "key_bytes": kb.value, "pt_bytes": pb.value}
