@@ -185,13 +185,19 @@ __global__ __launch_bounds__(256) void k_sum_partials_batch(const double* __rest
   acc[(size_t)p * tot + idx] = reduce(v, m);
 }
 
+// Workgroups go round-robin over the 8 XCDs; each XCD takes a contiguous
+// range of the (product, diagonal) list so that neighbouring diagonals of one
+// product, which read neighbouring columns of X, share its L2.
 template <int LOGN>
 __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_pt_batch(const EncodeArgs* __restrict__ args,
-                                                                       const int2* __restrict__ work,
+                                                                       const int2* __restrict__ work, int nwork,
                                                                        const BatchProd* __restrict__ prods, EncTabs et,
                                                                        LimbMap map, DevTabs tb) {
   __shared__ double2 s2[NttShape<LOGN>::LDS / 2];
-  const int2 wk = work[blockIdx.x];
+  const int per_xcd = (nwork + 7) / 8;
+  const int vt = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (vt >= nwork) return;
+  const int2 wk = work[vt];
   const EncodeArgs a = args[wk.x];
   double* out = prods[wk.x].pt_out + (size_t)wk.y * map.n * (1 << LOGN);
   encode_pt_body<LOGN>(a, wk.y, et, map, tb, s2, out);
@@ -201,7 +207,7 @@ template <int LOGN>
 __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_ct_batch(const EncodeArgs* __restrict__ args, EncTabs et,
                                                                        int64_t* __restrict__ msg) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PH = N / 2 / T;
-  __shared__ double2 s2[N / 2];
+  __shared__ double2 s2[NttShape<LOGN>::LDS / 2];
   const int c = blockIdx.x;
   double mreg[2 * PH];
   const EncodeArgs a = args[c];
@@ -305,8 +311,8 @@ hipError_t launch_sum_partials_batch(const LaunchCtx& L, const double* part, con
 template <int LOGN>
 static void enc_pt_batch_impl(const LaunchCtx& L, const EncodeArgs* args, const int2* work, int nwork,
                               const BatchProd* prods, const EncTabs& et, LimbMap map) {
-  hipLaunchKernelGGL(k_encode_pt_batch<LOGN>, dim3(nwork), dim3(NttShape<LOGN>::T), 0, L.stream, args, work, prods, et,
-                     map, L.tb);
+  hipLaunchKernelGGL(k_encode_pt_batch<LOGN>, dim3(8 * ((nwork + 7) / 8)), dim3(NttShape<LOGN>::T), 0, L.stream, args,
+                     work, nwork, prods, et, map, L.tb);
 }
 hipError_t launch_encode_pt_batch(const LaunchCtx& L, const EncodeArgs* args, const int2* work, int nwork,
                                   const BatchProd* prods, const EncTabs& et, LimbMap map) {

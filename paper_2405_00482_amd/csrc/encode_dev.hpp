@@ -14,6 +14,10 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// padded index of complex element i in LDS (one pad slot every 16): breaks
+// the bank conflicts of strided and bit-reversed access
+__device__ __forceinline__ int cpad(int i) { return i + (i >> 4); }
+
 __device__ __forceinline__ double round_half_away(double x) {
   const double r = __builtin_trunc(x + (x >= 0.0 ? 0.5 : -0.5));
   return r;
@@ -37,9 +41,9 @@ __device__ __forceinline__ void fft_dif_lds(double2* a, const double2* __restric
       const int i0 = (blk << (lhalf + 1)) + j, i1 = i0 + half;
       double2 w = tw[j << s];  // W_len^j = W_M^(j M/len)
       if (conj) w = cconj(w);
-      const double2 u = a[i0], v = a[i1];
-      a[i0] = make_double2(u.x + v.x, u.y + v.y);
-      a[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
+      const double2 u = a[cpad(i0)], v = a[cpad(i1)];
+      a[cpad(i0)] = make_double2(u.x + v.x, u.y + v.y);
+      a[cpad(i1)] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
     }
     __syncthreads();
   }
@@ -109,7 +113,7 @@ __device__ __forceinline__ void encode_to_regs(const EncodeArgs& a, int k, doubl
   const int tid = threadIdx.x;
   for (int s = tid; s < M; s += T) {
     const double v = CT ? ct_slot_value(a, k, s) : pt_slot_value(a, k, s);
-    z[et.slot2f[s]] = make_double2(v * scale, 0.0);
+    z[cpad(et.slot2f[s])] = make_double2(v * scale, 0.0);
   }
   __syncthreads();
   fft_dif_lds<LOGN>(z, et.fft_tw, false);
@@ -117,7 +121,7 @@ __device__ __forceinline__ void encode_to_regs(const EncodeArgs& a, int k, doubl
 #pragma unroll
   for (int u = 0; u < PH; ++u) {
     const int kk = tid + u * T;
-    const double2 w = cmul(z[brev(kk, LOGN - 1)], cconj(et.twist[kk]));
+    const double2 w = cmul(z[cpad(brev(kk, LOGN - 1))], cconj(et.twist[kk]));
     mreg[2 * u] = round_half_away(w.x * inv_m);
     mreg[2 * u + 1] = round_half_away(w.y * inv_m);
   }
@@ -135,14 +139,14 @@ __device__ __forceinline__ void encode_pt_body(const EncodeArgs& a, int k, const
   double mreg[2 * PH];
   if (a.kind == 2 && k == a.m) {
     // ROW indicator plaintext: 1 in slot 0 at scale q_(l-1)
-    for (int t = threadIdx.x; t < N / 2; t += T) s2[et.slot2f[t]] = make_double2(t == 0 ? a.ind_scale : 0.0, 0.0);
+    for (int t = threadIdx.x; t < N / 2; t += T) s2[cpad(et.slot2f[t])] = make_double2(t == 0 ? a.ind_scale : 0.0, 0.0);
     __syncthreads();
     fft_dif_lds<LOGN>(s2, et.fft_tw, false);
     const double inv_m = 1.0 / (double)(N / 2);
 #pragma unroll
     for (int u = 0; u < PH; ++u) {
       const int kk = threadIdx.x + u * T;
-      const double2 w = cmul(s2[brev(kk, LOGN - 1)], cconj(et.twist[kk]));
+      const double2 w = cmul(s2[cpad(brev(kk, LOGN - 1))], cconj(et.twist[kk]));
       mreg[2 * u] = round_half_away(w.x * inv_m);
       mreg[2 * u + 1] = round_half_away(w.y * inv_m);
     }

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_pt(EncodeArgs a, E
 template <int LOGN>
 __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_ct_msg(EncodeArgs a, EncTabs et, int64_t* __restrict__ msg) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PH = N / 2 / T;
-  __shared__ double2 s2[N / 2];
+  __shared__ double2 s2[NttShape<LOGN>::LDS / 2];
   const int c = blockIdx.x;
   double mreg[2 * PH];
   encode_to_regs<LOGN, true>(a, c, s2, mreg, et, a.scale);
@@ -49,7 +49,7 @@ template <int LOGN>
 __global__ __launch_bounds__(NttShape<LOGN>::T) void k_decode(const double* __restrict__ res, int lv, CrtTabs ct,
                                                               EncTabs et, double inv_scale, double* __restrict__ z) {
   constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T;
-  __shared__ double2 w[N / 2];
+  __shared__ double2 w[NttShape<LOGN>::LDS / 2];
   const int c = blockIdx.x;
   const double* base = res + (size_t)c * (lv + 1) * N;
   const int nl = lv + 1;
@@ -75,11 +75,11 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_decode(const double* __re
       for (int i = nl - 2; i >= 0; --i) acc = acc * ct.mods[i].q + v[i];
       val[h] = acc;
     }
-    w[k] = cmul(make_double2(val[0], val[1]), et.twist[k]);
+    w[cpad(k)] = cmul(make_double2(val[0], val[1]), et.twist[k]);
   }
   __syncthreads();
   fft_dif_lds<LOGN>(w, et.fft_tw, true);
-  for (int j = threadIdx.x; j < M; j += T) z[(size_t)c * M + j] = w[brev(et.slot2f[j], LOGN - 1)].x * inv_scale;
+  for (int j = threadIdx.x; j < M; j += T) z[(size_t)c * M + j] = w[cpad(brev(et.slot2f[j], LOGN - 1))].x * inv_scale;
 }
 
 // lazy rotate-and-sum / read-out of the decoded slots (Sec. 4.3)
