@@ -22,6 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# timer class -> kernel symbol (template instances share the prefix)
+KERNEL_SYMBOL = {"fused_diagonal": "k_diag_batch", "encode_pt": "k_encode_pt_batch", "modup": "k_modup",
+                 "moddown": "k_moddown"}
 
 
 def log(msg):
@@ -61,6 +64,35 @@ def cpu_baseline(name, shapes, n_diag, seeds):
                       f"{dt:.1f} s single-threaded; rotation-key generation excluded"}
 
 
+def copy_calibration(nbytes=256 << 20, reps=3):
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "dispatches": reps}), flush=True)
+
+
+def measured_traffic(launch_key: str, kernel: str):
+    """HBM bytes per dispatch from the committed counter summary, or None when
+    the summary is missing, was taken for another launch configuration, or
+    the kernel sources changed since."""
+    from paper_2405_00482_amd.profile_summary import kernel_source_hash
+    f = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic_C3.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        rec = json.load(fh)
+    if rec.get("workload") != launch_key or rec.get("source_hash") != kernel_source_hash():
+        return None
+    hits = [v for k, v in rec["kernels"].items() if k.split("<")[0] == kernel]
+    if not hits:
+        return None
+    n = sum(v["dispatches"] for v in hits)
+    return sum(v["traffic_bytes"] * v["dispatches"] for v in hits) / n
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,10 +106,15 @@ def main():
     ap.add_argument("--vec", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=32)
     ap.add_argument("--percall-steps", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     from paper_2405_00482_amd import pvfl
@@ -171,6 +208,8 @@ def main():
     dom = max(kt, key=lambda k: kt[k]["total_ms"])
     dk = kt[dom]
     achieved = dk["bytes"] / (dk["total_ms"] * 1e-3) / 1e9 if dk["total_ms"] > 0 else 0.0
+    launch_key = f"C3 x{len(shapes)}, group {args.group}, chunk {args.chunk}, vec {args.vec}"
+    traffic = measured_traffic(launch_key, KERNEL_SYMBOL[dom])
     ms_percall = None
     if args.percall_steps > 0:
         ms_percall = timed(step_percall, args.percall_steps)
@@ -194,8 +233,10 @@ def main():
                                f"(group {args.group}, chunk {args.chunk}, vec {args.vec}){'' if args.no_graph else ', HIP graph'}",
                    "macs_per_step": macs, "max_rel_err": max(errs),
                    "percall_ms_per_step": ms_percall, "instrumented_ms_per_step": ms_instrumented},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": dk["bytes"] / max(dk["launches"], 1),
+                     "avg_launch_us": dk["total_ms"] * 1e3 / max(dk["launches"], 1)},
         "kernels": {k: {"ms_per_step": v["ms_per_step"], "launches_per_step": v["launches"] / args.steps,
                         "algorithmic_GBps": v["bytes"] / max(v["total_ms"] * 1e-3, 1e-12) / 1e9}
                     for k, v in kt.items()},

@@ -88,6 +88,10 @@ typedef struct {
   int32_t ras_in_ct;     /* DIAG with m < n: 1 = rotate-and-sum inside the ciphertext, 0 = lazy RaS after decryption */
   int32_t pack;          /* CTMAT: columns of W per plaintext (1 = Alg. 3 literal) */
   double pt_log2_scale;  /* plaintext scale exponent; <= 0 means the context's default */
+  int32_t bsgs;          /* HYBRID with lazy ModDown: baby-step size b (power of two, 2 <= b <= m'/2) of a
+                            baby-step/giant-step split of the diagonal sum (Halevi-Shoup 2018; not in the paper):
+                            b - 1 hoisted baby rotations, m'/b - 1 giant rotations per block, each giant inner
+                            sum brought down by its own ModDown.  0 = every rotation hoisted (Sec. 4, O4). */
 } pvfl_plan_opts;
 
 typedef struct {
@@ -98,6 +102,9 @@ typedef struct {
   int32_t n_pts, pt_limbs, ct_in, ct_out, in_level, out_level, n_galois;
   int64_t n_add, n_mult, n_rot, n_hstrot; /* Table 2 / Table 3 counts of this plan */
   double out_log2_scale;
+  int32_t bsgs;          /* baby-step size (0 = none) */
+  int32_t n_modup;       /* digit decompositions (ModUp) one product runs */
+  int32_t n_moddown;     /* ModDowns of a ciphertext one product runs */
 } pvfl_plan_info;
 
 const char* pvfl_last_error(void);
@@ -230,6 +237,27 @@ pvfl_status pvfl_batch_run(pvfl_batch* batch, const pvfl_sk* sk, uint64_t seed, 
 /* work items of the fused kernel and its algorithmic key / plaintext bytes */
 pvfl_status pvfl_batch_info(const pvfl_batch* batch, int64_t* n_work_items, double* key_bytes, double* pt_bytes);
 void pvfl_batch_destroy(pvfl_batch* batch);
+
+/* Latency-model network of the plan selector: a 3-layer perceptron
+ * y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 in FP32 (n_in <= 64 inputs,
+ * hidden <= 64), trained on measured plan latencies by hand-written HIP
+ * forward, backward and Adam kernels.  Parameters are one FP32 vector laid out
+ * W1[hidden][n_in], b1, W2[hidden][hidden], b2, w3, b3 (He-uniform init from
+ * seed, zero biases).  x: [batch][n_in], t and y: [batch] device arrays.
+ * pvfl_mlp_grad: gradient of the mean squared error (1/B) sum (y - t)^2 into
+ *   grad_dev (n_params floats) and the loss into loss_dev (either may be NULL).
+ * pvfl_mlp_train_step: one Adam step (beta1 0.9, beta2 0.999, eps 1e-8). */
+typedef struct pvfl_mlp pvfl_mlp;
+pvfl_status pvfl_mlp_create(int32_t n_in, int32_t hidden, int32_t max_batch, uint64_t seed, pvfl_mlp** out);
+int32_t pvfl_mlp_num_params(const pvfl_mlp* mlp);
+pvfl_status pvfl_mlp_get_params(const pvfl_mlp* mlp, float* out_dev, void* stream);
+pvfl_status pvfl_mlp_set_params(pvfl_mlp* mlp, const float* in_dev, void* stream);
+pvfl_status pvfl_mlp_forward(const pvfl_mlp* mlp, const float* x_dev, int32_t batch, float* y_dev, void* stream);
+pvfl_status pvfl_mlp_grad(pvfl_mlp* mlp, const float* x_dev, const float* t_dev, int32_t batch, float* grad_dev,
+                          float* loss_dev, void* stream);
+pvfl_status pvfl_mlp_train_step(pvfl_mlp* mlp, const float* x_dev, const float* t_dev, int32_t batch, float lr,
+                                float* loss_dev, void* stream);
+void pvfl_mlp_destroy(pvfl_mlp* mlp);
 
 /* Optional kernel timing for measurement.  When enabled, every launch of the
  * timed kernel classes is bracketed by HIP events recorded on the launch's

@@ -399,21 +399,7 @@ def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool) 
     term_cache = {}
     for (c, i, k, b) in terms:
         if (c, i) not in term_cache:
-            ct = cts[c]
-            if i == 0:
-                t0 = np.zeros((len(QPp), N), dtype=np.uint64)
-                t1 = np.zeros_like(t0)
-                for r in range(lv + 1):
-                    t0[r] = O.poly_scalar(ct.c0[r], Pint % Qp[r], Qp[r])
-                    t1[r] = O.poly_scalar(ct.c1[r], Pint % Qp[r], Qp[r])
-            else:
-                g = O.galois_rotl(i, N)
-                u0, u1 = O.inner_product(params, lv, digits[c], keys[g], g)
-                c0r = O.automorphism_ct_part(params, lv, ct.c0, g)
-                t0, t1 = u0, u1
-                for r in range(lv + 1):
-                    t0[r] = O.poly_add(t0[r], O.poly_scalar(c0r[r], Pint % Qp[r], Qp[r]), Qp[r])
-            term_cache[(c, i)] = (t0, t1)
+            term_cache[(c, i)] = lazy_term(params, cts[c], digits[c], keys, i)
         t0, t1 = term_cache[(c, i)]
         pt = O.reduce_signed(pt_ints[k], QPp)
         for r, mod in enumerate(QPp):
@@ -421,6 +407,29 @@ def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool) 
             acc1[b][r] = O.poly_add(acc1[b][r], O.poly_mul(pt[r], t1[r], mod), mod)
     return [O.Ciphertext(O.moddown(params, lv, acc0[b]), O.moddown(params, lv, acc1[b]), lv)
             for b in range(n_out)]
+
+
+def lazy_term(params: O.Params, ct, digits, keys: dict, i: int):
+    """RotL(ct, i) over Q u P before its ModDown: (P*phi(c0) + u0, u1) with
+    (u0, u1) the key inner product of phi(digits); i = 0 gives (P*c0, P*c1)."""
+    N = params.N
+    lv = ct.level
+    Qp = params.q[: lv + 1]
+    QPp = params.qp(lv)
+    Pint = params.P()
+    if i == 0:
+        t0 = np.zeros((len(QPp), N), dtype=np.uint64)
+        t1 = np.zeros_like(t0)
+        for r in range(lv + 1):
+            t0[r] = O.poly_scalar(ct.c0[r], Pint % Qp[r], Qp[r])
+            t1[r] = O.poly_scalar(ct.c1[r], Pint % Qp[r], Qp[r])
+        return t0, t1
+    g = O.galois_rotl(i, N)
+    u0, u1 = O.inner_product(params, lv, digits, keys[g], g)
+    c0r = O.automorphism_ct_part(params, lv, ct.c0, g)
+    for r in range(lv + 1):
+        u0[r] = O.poly_add(u0[r], O.poly_scalar(c0r[r], Pint % Qp[r], Qp[r]), Qp[r])
+    return u0, u1
 
 
 def hybrid_pt_ints(params: O.Params, plan: HybridPlan, X, scale: float) -> list:
@@ -438,6 +447,91 @@ def hybrid_ct_ints(params: O.Params, plan: HybridPlan, y, scale: float) -> list:
 
 def hybrid_galois(plan, N: int) -> list:
     return [O.galois_rotl(i, N) for i in range(1, plan.mprime)]
+
+
+# ---------------------------------------------------------------------------
+# baby-step/giant-step schedule of the hybrid's diagonal sum (Halevi-Shoup
+# 2018; not in the paper, one of the rotation schedules the planner weighs).
+# With diagonal i = j*bs + k (k < bs, j < g = m'/bs):
+#     sum_i pt_i * RotL(ct, i) = sum_j RotL( sum_k RotL(pt_i, -j*bs) * RotL(ct, k), j*bs )
+# The bs - 1 baby rotations share one ModUp and stay over Q u P (as in the
+# lazy hoisted form); every inner sum is brought down to Q by its own ModDown
+# and, for j > 0, rotated by j*bs with its own key switch (ModUp of the
+# sum's c1, phi on the digits, ModDown).
+# ---------------------------------------------------------------------------
+def bsgs_valid(plan: HybridPlan, bs: int) -> bool:
+    return bs >= 2 and (bs & (bs - 1)) == 0 and 2 * bs <= plan.mprime
+
+
+def bsgs_pt_slots(plan: HybridPlan, X, b: int, c: int, i: int, bs: int) -> np.ndarray:
+    """diagonal i pre-rotated right by its giant step: RotL(pt_i, -(i // bs) * bs)"""
+    return np.roll(hybrid_pt_slots(plan, X, b, c, i), (i // bs) * bs)
+
+
+def bsgs_pt_ints(params: O.Params, plan: HybridPlan, X, scale: float, bs: int) -> list:
+    out = []
+    for b in range(plan.row_blocks):
+        for c in range(plan.col_blocks):
+            for i in range(plan.mprime):
+                out.append(O.encode(bsgs_pt_slots(plan, X, b, c, i, bs), params.N, scale))
+    return out
+
+
+def bsgs_galois(plan: HybridPlan, N: int, bs: int) -> list:
+    g = plan.mprime // bs
+    gs = [O.galois_rotl(k, N) for k in range(1, bs)] + [O.galois_rotl(j * bs, N) for j in range(1, g)]
+    return sorted(set(gs))
+
+
+def simulate_hybrid_bsgs(plan: HybridPlan, X, y, bs: int) -> np.ndarray:
+    """Cleartext FP64 run of the baby-step/giant-step evaluation order."""
+    S = plan.slots
+    g = plan.mprime // bs
+    cts = [hybrid_ct_slots(plan, y, c) for c in range(plan.col_blocks)]
+    acc = [np.zeros(S) for _ in range(plan.row_blocks)]
+    for b in range(plan.row_blocks):
+        for c in range(plan.col_blocks):
+            for j in range(g):
+                inner = np.zeros(S)
+                for k in range(bs):
+                    inner += bsgs_pt_slots(plan, X, b, c, j * bs + k, bs) * np.roll(cts[c], -k)
+                acc[b] += np.roll(inner, -j * bs)
+    return hybrid_lazy_ras(plan, acc)
+
+
+def hybrid_matmul_bsgs(params: O.Params, plan: HybridPlan, cts, pt_ints, keys: dict, bs: int) -> list:
+    """Evaluate the hybrid plan in baby-step/giant-step order; pt_ints from
+    bsgs_pt_ints (pre-rotated diagonals)."""
+    assert bsgs_valid(plan, bs)
+    N = params.N
+    lv = cts[0].level
+    QPp = params.qp(lv)
+    g = plan.mprime // bs
+    digits = {c: O.modup(params, lv, cts[c].c1) for c in range(plan.col_blocks)}
+    baby = {}
+    outs = []
+    for b in range(plan.row_blocks):
+        out = None
+        for c in range(plan.col_blocks):
+            for j in range(g):
+                acc0 = np.zeros((len(QPp), N), dtype=np.uint64)
+                acc1 = np.zeros_like(acc0)
+                for k in range(bs):
+                    if (c, k) not in baby:
+                        baby[(c, k)] = lazy_term(params, cts[c], digits[c], keys, k)
+                    t0, t1 = baby[(c, k)]
+                    i = j * bs + k
+                    pt = O.reduce_signed(pt_ints[(b * plan.col_blocks + c) * plan.mprime + i], QPp)
+                    for r, mod in enumerate(QPp):
+                        acc0[r] = O.poly_add(acc0[r], O.poly_mul(pt[r], t0[r], mod), mod)
+                        acc1[r] = O.poly_add(acc1[r], O.poly_mul(pt[r], t1[r], mod), mod)
+                part = O.Ciphertext(O.moddown(params, lv, acc0), O.moddown(params, lv, acc1), lv)
+                if j > 0:
+                    gal = O.galois_rotl(j * bs, N)
+                    part = O.hoisted_rotate(params, part, O.modup(params, lv, part.c1), keys[gal])
+                out = part if out is None else O.ct_add(params, out, part)
+        outs.append(out)
+    return outs
 
 
 def row_matmul(params: O.Params, plan: RowPlan, ct, pt_ints, ind_ints, keys: dict):

@@ -115,8 +115,9 @@ extern "C" pvfl_status pvfl_batch_create(pvfl_ctx* c, int32_t count, const pvfl_
     const pvfl_plan* p = plans[k];
     if (!p || p->ctx != c) return fail(PVFL_E_INVALID, "plan belongs to another context");
     const bool ok_kind = p->opts.kind == PVFL_PLAN_HYBRID || (p->opts.kind == PVFL_PLAN_DIAG && p->ras_rots.empty());
-    if (!ok_kind || !p->opts.lazy_moddown || p->info.ct_in != 1 || p->info.ct_out != 1)
-      return fail(PVFL_E_PLAN, "batched products must be lazy HYBRID/DIAG plans with one input and one output ciphertext");
+    if (!ok_kind || !p->opts.lazy_moddown || p->info.ct_in != 1 || p->info.ct_out != 1 || p->info.bsgs != 0)
+      return fail(PVFL_E_PLAN, "batched products must be lazy, hoisted HYBRID/DIAG plans with one input and one "
+                               "output ciphertext");
     if (p->lv != b->lv) return fail(PVFL_E_LEVEL, "batched products must share the level");
     if (p->pt_scale != p0->pt_scale) return fail(PVFL_E_PLAN, "batched products must share the plaintext scale");
     if (!p->galois.empty()) {

@@ -83,6 +83,7 @@ struct pvfl_plan {
   std::vector<uint32_t> galois;
   // device tables
   int* iota_dev = nullptr;     // [max(mprime, 1)] = 0..mprime-1
+  int* rot_dev = nullptr;      // BSGS: [mprime] baby rotation of diagonal i (i mod bsgs)
   int chunk = 1, nchunk = 1;   // diagonal chunking of the fused kernel
   // DIAG plan: in-ciphertext RaS rotations; ROW plan: per-row data
   std::vector<int> ras_rots;

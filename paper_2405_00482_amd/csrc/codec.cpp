@@ -94,7 +94,7 @@ EncodeArgs geometry_of(const pvfl_plan* p, const double* X, int64_t ld) {
   a.n_out = I.n_out;
   a.n_out_cts = I.ct_out;
   switch (I.kind) {
-    case PVFL_PLAN_HYBRID: a.bm = p->bm; a.bn = p->bn; break;
+    case PVFL_PLAN_HYBRID: a.bm = p->bm; a.bn = p->bn; a.bsgs = p->opts.bsgs; break;
     case PVFL_PLAN_DIAG:
     case PVFL_PLAN_CTMAT: a.bm = I.m_pad; a.bn = I.n_pad; a.width = std::max(I.m_pad, I.n_pad); break;
     case PVFL_PLAN_ROW: a.bm = I.m_pad; a.bn = I.n_pad; break;

@@ -26,6 +26,7 @@ struct EncodeArgs {
   int bm, bn, mprime, col_blocks, width, pack, n_out, n_out_cts, slots;
   double scale;    // encoding scale
   double ind_scale;  // ROW: scale of the indicator plaintext
+  int bsgs;          // HYBRID: baby-step size; diagonal i is stored rotated right by (i / bsgs) * bsgs
 };
 
 hipError_t launch_encode_pt(const LaunchCtx& L, const EncodeArgs& a, const EncTabs& et, LimbMap map, int count,

@@ -57,6 +57,7 @@ __device__ __forceinline__ double pt_slot_value(const EncodeArgs& a, int k, int 
     case 0: {  // HYBRID: block (b, c), diagonal i; slot s = g bn + j
       const int per = a.col_blocks * a.mprime;
       const int b = k / per, c = (k / a.mprime) % a.col_blocks, i = k % a.mprime;
+      if (a.bsgs > 0) s = (s - (i / a.bsgs) * a.bsgs + a.slots) & (a.slots - 1);  // pre-rotation by the giant step
       const int g = s / a.bn, j = s % a.bn;
       const int rr = g * a.mprime + (j % a.mprime);
       if (rr >= a.bm) return 0.0;

@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void k_diag_lazy(DiagArgs a) {
   int cnt = 0;
   for (int i = i0; i < i1; ++i) {
     const double p = a.pt[(size_t)a.pt_index[i] * K * N + limbN + t];
-    if (i == 0) {
+    if (a.rot[i] == 0) {
       if (isq) {
         acc0 += mulmod(p, a.pc[limbN + t], m);
         acc1 += mulmod(p, a.pc[(size_t)(a.lv + 1) * N + limbN + t], m);

@@ -68,7 +68,7 @@ struct DiagArgs {
   int key_limb[kMaxLimbs];
   const double* pt;        // [n_pts][K][N]
   const int* pt_index;     // [mprime]
-  const int* rot;          // [mprime] rotation amount of diagonal i
+  const int* rot;          // [mprime] rotation amount of diagonal i (0: the unrotated P*c term)
   const int* slot_of_rot;  // [N/2] rotation amount -> key index
   const double* keys;
   const double* digits;    // [beta][K][N]

@@ -45,6 +45,7 @@ static int ilog2(int x) {
 
 pvfl_plan::~pvfl_plan() {
   if (iota_dev) hipFree(iota_dev);
+  if (rot_dev) hipFree(rot_dev);
   if (own_ws) hipFree(own_ws);
 }
 
@@ -83,6 +84,7 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
   const double lds = c->log2_scale + std::log2(p->pt_scale);
   I.out_log2_scale = lds;
   const bool lazy = o->lazy_moddown != 0;
+  if (o->bsgs != 0 && o->kind != PVFL_PLAN_HYBRID) return fail(PVFL_E_PLAN, "bsgs applies to HYBRID plans only");
   switch (o->kind) {
     case PVFL_PLAN_HYBRID: {
       const int mp = I.m_pad, np = I.n_pad;
@@ -99,11 +101,28 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
       I.n_pts = (int)p->terms.size();
       I.ct_in = I.col_blocks;
       I.ct_out = I.row_blocks;
-      for (int i = 1; i < I.mprime; ++i) p->galois.push_back(galois_rotl(i, N));
       I.n_mult = I.n_pts;
       I.n_add = I.n_pts - I.row_blocks;
-      I.n_rot = 0;
-      I.n_hstrot = (int64_t)I.col_blocks * (I.mprime - 1);
+      if (o->bsgs != 0) {
+        const int bs = o->bsgs;
+        if (!lazy) return fail(PVFL_E_PLAN, "the baby-step/giant-step schedule needs lazy ModDown");
+        if (bs < 2 || (bs & (bs - 1)) != 0 || 2 * bs > I.mprime)
+          return fail(PVFL_E_PLAN, "bsgs must be a power of two with 2 <= bsgs <= m'/2");
+        const int g = I.mprime / bs;
+        for (int k = 1; k < bs; ++k) p->galois.push_back(galois_rotl(k, N));
+        for (int j = 1; j < g; ++j) p->galois.push_back(galois_rotl(j * bs, N));
+        I.bsgs = bs;
+        I.n_hstrot = (int64_t)I.col_blocks * (bs - 1);
+        I.n_rot = (int64_t)I.row_blocks * I.col_blocks * (g - 1);
+        I.n_modup = I.col_blocks + (int)I.n_rot;
+        I.n_moddown = I.row_blocks * I.col_blocks * g + (int)I.n_rot;
+      } else {
+        for (int i = 1; i < I.mprime; ++i) p->galois.push_back(galois_rotl(i, N));
+        I.n_rot = 0;
+        I.n_hstrot = (int64_t)I.col_blocks * (I.mprime - 1);
+        I.n_modup = I.mprime > 1 ? I.col_blocks : 0;
+        I.n_moddown = lazy ? I.row_blocks : (int)I.n_hstrot * I.row_blocks;
+      }
       break;
     }
     case PVFL_PLAN_DIAG: {
@@ -128,6 +147,8 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
       I.n_rot = (int64_t)p->ras_rots.size();
       I.n_add = nd - 1 + I.n_rot;
       I.n_hstrot = nd - 1;
+      I.n_modup = (nd > 1 ? 1 : 0) + (int)I.n_rot;
+      I.n_moddown = (lazy ? 1 : nd - 1) + (int)I.n_rot;
       break;
     }
     case PVFL_PLAN_ROW: {
@@ -146,6 +167,7 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
       I.n_rot = (int64_t)o->m * logn + o->m - 1;
       I.n_add = I.n_rot;
       I.n_hstrot = 0;
+      I.n_modup = I.n_moddown = (int)I.n_rot;
       I.out_level = lv - 2;
       I.out_log2_scale = lds - std::log2((double)c->primes[lv]);
       break;
@@ -185,6 +207,14 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
   for (int i = 0; i < mprime; ++i) iota[i] = i;
   if (hipMalloc((void**)&p->iota_dev, sizeof(int) * mprime) != hipSuccess) return fail(PVFL_E_NOMEM, "plan tables");
   HIP_TRY(hipMemcpy(p->iota_dev, iota.data(), sizeof(int) * mprime, hipMemcpyHostToDevice));
+  if (I.bsgs) {
+    // one fused-kernel chunk per giant step: its partial is that step's inner sum
+    p->chunk = I.bsgs;
+    p->nchunk = mprime / I.bsgs;
+    for (int i = 0; i < mprime; ++i) iota[i] = i % I.bsgs;
+    if (hipMalloc((void**)&p->rot_dev, sizeof(int) * mprime) != hipSuccess) return fail(PVFL_E_NOMEM, "plan tables");
+    HIP_TRY(hipMemcpy(p->rot_dev, iota.data(), sizeof(int) * mprime, hipMemcpyHostToDevice));
+  }
   *out = p.release();
   return PVFL_OK;
 }
@@ -223,8 +253,12 @@ static size_t ws_doubles(const pvfl_plan* p) {
   switch (p->opts.kind) {
     case PVFL_PLAN_HYBRID:
     case PVFL_PLAN_DIAG:
-      if (p->opts.lazy_moddown)
-        return digits + Q + 2 * Q + (size_t)p->info.col_blocks * p->nchunk * 2 * KN + 2 * KN + ydown + 4 * Q;
+      if (p->opts.lazy_moddown) {
+        const size_t CB = p->info.col_blocks, g = p->info.bsgs ? p->nchunk : 1;
+        const size_t bsgs = p->info.bsgs ? g * 2 * Q + digits + 2 * Q + Q : 0;
+        // + 4Q at the end: in-ciphertext RaS temporaries
+        return CB * digits + Q + CB * 2 * Q + CB * p->nchunk * 2 * KN + 2 * KN + g * ydown + bsgs + 4 * Q;
+      }
       return digits + Q + 2 * KN + ydown + 2 * Q + 4 * Q;
     case PVFL_PLAN_ROW:
       return 8 * Q;
@@ -270,16 +304,33 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
                                  double* out, double* ws, void* stream) {
   pvfl_ctx* c = p->ctx;
   const int N = c->N, lv = p->lv, K = p->K;
-  const size_t Q = (size_t)(lv + 1) * N, KN = (size_t)K * N;
+  const int CB = p->info.col_blocks, RB = p->info.row_blocks;
+  const int bs = p->info.bsgs, g = bs ? p->nchunk : 1;
+  const size_t Q = (size_t)(lv + 1) * N, KN = (size_t)K * N, DG = (size_t)p->beta * KN;
   const KsLevel& kl = c->ks_host[lv];
-  double* digits = ws;
-  double* yup = digits + (size_t)p->beta * KN;
-  double* pc = yup + Q;
-  double* part = pc + 2 * Q;
-  double* acc = part + (size_t)p->info.col_blocks * p->nchunk * 2 * KN;
-  double* ydown = acc + 2 * KN;
+  // workspace, in the order ws_doubles counts it
+  double* digits = ws;                                  // [CB][beta][K][N]
+  double* yup = digits + CB * DG;                       // [lv+1][N]
+  double* pc = yup + Q;                                 // [CB][2][lv+1][N]: P*c of every input
+  double* part = pc + CB * 2 * Q;                       // [CB][nchunk][2][K][N]
+  double* acc = part + (size_t)CB * p->nchunk * 2 * KN; // [2][K][N]
+  double* ydown = acc + 2 * KN;                         // [2g][alpha][N]
+  double* cj = ydown + (size_t)2 * g * c->alpha * N;    // BSGS: [g][2][lv+1][N] giant-step inner sums
+  double* dig2 = cj + (bs ? g * 2 * Q : 0);             // BSGS: digits of one inner sum
+  double* v = dig2 + (bs ? DG : 0);                     // BSGS: key-switched part [2][lv+1][N]
+  double* rct = v + (bs ? 2 * Q : 0);                   // BSGS: phi(c0) [lv+1][N]
   LaunchCtx L = launch_ctx(c, stream);
   const int mprime = p->info.mprime;
+  // one ModUp and one P*c per input ciphertext, shared by every row block
+  for (int cb = 0; cb < CB; ++cb) {
+    const double* ct = ct_in + (size_t)cb * 2 * Q;
+    if (mprime > 1) {
+      KernelTimer kt(c, stream, PVFL_TIMING_MODUP, 8.0 * (double)(Q + DG));
+      HIP_TRY(launch_modup(L, ct, 0, 1, lv, c->ks_dev + lv, kl.n_tasks, yup, digits + cb * DG, 0));
+      kt.stop();
+    }
+    HIP_TRY(launch_scale_by_p(L, ct, lv, N, c->pmod_dev, pc + cb * 2 * Q));
+  }
   DiagArgs a{};
   a.N = N;
   a.K = K;
@@ -289,47 +340,65 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
   a.chunk = p->chunk;
   a.mods = c->tabs.mods;
   const LimbMap lp = qp_map(c, lv, true);
+  const LimbMap qm = qp_map(c, lv, false);
   for (int r = 0; r < K; ++r) {
     a.limb_prime[r] = lp.idx[r];
     a.key_limb[r] = lp.idx[r];
   }
   a.pt_index = p->iota_dev;
-  a.rot = p->iota_dev;
-  a.digits = digits;
-  a.pc = pc;
+  a.rot = bs ? p->rot_dev : p->iota_dev;
   if (keys) {
     a.keys = keys->keys;
     a.key_limbs = keys->key_limbs;
     a.key_stride = keys->key_stride;
     a.slot_of_rot = keys->slot_of_rot_dev;
   }
-  for (int b = 0; b < p->info.row_blocks; ++b) {
+  // algorithmic bytes of one fused launch: every key and plaintext limb once,
+  // digits and P*c once, partials written
+  const int n_keys = bs ? bs - 1 : mprime - 1;
+  const double diag_bytes = 8.0 * ((double)n_keys * 2 * p->beta * KN + (double)mprime * KN + (double)DG + 2.0 * Q +
+                                   (double)p->nchunk * 2 * KN);
+  for (int b = 0; b < RB; ++b) {
+    double* ob = out + (size_t)b * 2 * Q;
+    if (bs) HIP_TRY(launch_fill_zero(L, ob, 2 * Q));
     int z = 0;
-    for (int cb = 0; cb < p->info.col_blocks; ++cb) {
-      const double* ct = ct_in + (size_t)cb * 2 * Q;
-      if (mprime > 1) {
-        KernelTimer kt(c, stream, PVFL_TIMING_MODUP, 8.0 * (double)(Q + (size_t)p->beta * KN));
-        HIP_TRY(launch_modup(L, ct, 0, 1, lv, c->ks_dev + lv, kl.n_tasks, yup, digits, 0));
-        kt.stop();
-      }
-      HIP_TRY(launch_scale_by_p(L, ct, lv, N, c->pmod_dev, pc));
-      a.pt = pts + (size_t)(b * p->info.col_blocks + cb) * mprime * KN;
+    for (int cb = 0; cb < CB; ++cb) {
+      a.digits = digits + cb * DG;
+      a.pc = pc + cb * 2 * Q;
+      a.pt = pts + (size_t)(b * CB + cb) * mprime * KN;
       a.part = part + (size_t)z * 2 * KN;
       {
-        // algorithmic bytes: every key and plaintext limb once, digits and P*c once, partials written
-        const double key_bytes = 8.0 * (double)(mprime - 1) * 2 * p->beta * KN;
-        const double bytes = key_bytes + 8.0 * ((double)mprime * KN + (double)p->beta * KN + 2.0 * Q +
-                                                 (double)p->nchunk * 2 * KN);
-        KernelTimer kt(c, stream, PVFL_TIMING_DIAG, bytes);
+        KernelTimer kt(c, stream, PVFL_TIMING_DIAG, diag_bytes);
         HIP_TRY(launch_diag_lazy(L, a, p->nchunk));
         kt.stop();
       }
-      z += p->nchunk;
+      if (!bs) {
+        z += p->nchunk;
+        continue;
+      }
+      // every giant step's inner sum down to Q at once, then rotated by j*bs and added
+      {
+        KernelTimer kt(c, stream, PVFL_TIMING_MODDOWN, 8.0 * (double)g * (2 * KN + 2 * Q));
+        HIP_TRY(launch_moddown(L, a.part, 2 * g, lv, c->alpha, c->ks_dev + lv, ydown, cj));
+        kt.stop();
+      }
+      HIP_TRY(launch_add_limbs(L, ob, cj, 2 * (lv + 1), N, qm, ob));
+      for (int j = 1; j < g; ++j) {
+        const double* cjj = cj + (size_t)j * 2 * Q;
+        const int rot = j * bs;
+        HIP_TRY(launch_modup(L, cjj, 0, 1, lv, c->ks_dev + lv, kl.n_tasks, yup, dig2, 0));
+        pvfl_status st = keyswitch_digits(c, keys, lv, dig2, rot, rot, acc, ydown, v, stream);
+        if (st != PVFL_OK) return st;
+        HIP_TRY(launch_automorph(L, cjj, lv + 1, N, rot, rct));
+        HIP_TRY(launch_add_limbs(L, ob, rct, lv + 1, N, qm, ob));
+        HIP_TRY(launch_add_limbs(L, ob, v, 2 * (lv + 1), N, qm, ob));
+      }
     }
+    if (bs) continue;
     HIP_TRY(launch_sum_partials(L, part, z, K, N, lp, acc));
     {
       KernelTimer kt(c, stream, PVFL_TIMING_MODDOWN, 8.0 * (double)(2 * KN + 2 * Q));
-      HIP_TRY(launch_moddown(L, acc, 2, lv, c->alpha, c->ks_dev + lv, ydown, out + (size_t)b * 2 * Q));
+      HIP_TRY(launch_moddown(L, acc, 2, lv, c->alpha, c->ks_dev + lv, ydown, ob));
       kt.stop();
     }
   }

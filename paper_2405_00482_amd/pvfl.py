@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("n_out", ctypes.c_int32),
                 ("level", ctypes.c_int32), ("lazy_moddown", ctypes.c_int32), ("ras_in_ct", ctypes.c_int32),
-                ("pack", ctypes.c_int32), ("pt_log2_scale", ctypes.c_double)]
+                ("pack", ctypes.c_int32), ("pt_log2_scale", ctypes.c_double), ("bsgs", ctypes.c_int32)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -51,7 +51,8 @@ class PlanInfo(ctypes.Structure):
                                               "row_blocks", "col_blocks", "n_pts", "pt_limbs", "ct_in", "ct_out",
                                               "in_level", "out_level", "n_galois")] + \
                [(n, ctypes.c_int64) for n in ("n_add", "n_mult", "n_rot", "n_hstrot")] + \
-               [("out_log2_scale", ctypes.c_double)]
+               [("out_log2_scale", ctypes.c_double)] + \
+               [(n, ctypes.c_int32) for n in ("bsgs", "n_modup", "n_moddown")]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -95,6 +96,12 @@ def lib():
             "pvfl_encrypt": [_VP, _VP, _VP, ctypes.c_int64, u64, _VP, _VP],
             "pvfl_decrypt_decode": [_VP, _VP, _VP, _VP, _VP],
             "pvfl_timing_enable": [_VP, i32],
+            "pvfl_mlp_create": [i32, i32, i32, u64, ctypes.POINTER(_VP)],
+            "pvfl_mlp_get_params": [_VP, _VP, _VP],
+            "pvfl_mlp_set_params": [_VP, _VP, _VP],
+            "pvfl_mlp_forward": [_VP, _VP, i32, _VP, _VP],
+            "pvfl_mlp_grad": [_VP, _VP, _VP, i32, _VP, _VP, _VP],
+            "pvfl_mlp_train_step": [_VP, _VP, _VP, i32, ctypes.c_float, _VP, _VP],
             "pvfl_batch_create": [_VP, i32, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                   ctypes.POINTER(_VP), _VP, ctypes.POINTER(BatchOpts), ctypes.POINTER(_VP)],
@@ -116,8 +123,10 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [_VP]
             f.restype = sz
+        L.pvfl_mlp_num_params.argtypes = [_VP]
+        L.pvfl_mlp_num_params.restype = i32
         for name in ("pvfl_context_destroy", "pvfl_sk_destroy", "pvfl_rotkeys_destroy", "pvfl_plan_destroy",
-                     "pvfl_batch_destroy"):
+                     "pvfl_batch_destroy", "pvfl_mlp_destroy"):
             f = getattr(L, name)
             f.argtypes = [_VP]
             f.restype = None
@@ -197,8 +206,8 @@ class Context(_Handle):
         return RotKeys(h, list(g), keep=(self,))
 
     def plan(self, kind: int, m: int, n: int, n_out: int = 0, level: int = -1, lazy: bool = True,
-             ras_in_ct: bool = False, pack: int = 1, pt_log2_scale: float = 0.0) -> "Plan":
-        o = PlanOpts(kind, m, n, n_out, level, int(lazy), int(ras_in_ct), pack, pt_log2_scale)
+             ras_in_ct: bool = False, pack: int = 1, pt_log2_scale: float = 0.0, bsgs: int = 0) -> "Plan":
+        o = PlanOpts(kind, m, n, n_out, level, int(lazy), int(ras_in_ct), pack, pt_log2_scale, bsgs)
         h = _VP()
         _check(lib().pvfl_plan_create(self.h, ctypes.byref(o), ctypes.byref(h)))
         return Plan(h, self)
@@ -339,3 +348,55 @@ class Batch(_Handle):
         n, kb, pb = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
         _check(lib().pvfl_batch_info(self.h, ctypes.byref(n), ctypes.byref(kb), ctypes.byref(pb)))
         return {"work_items": n.value, "key_bytes": kb.value, "pt_bytes": pb.value}
+
+
+class Mlp(_Handle):
+    """The plan selector's latency network (FP32, GPU-trained)."""
+    _destroy = "pvfl_mlp_destroy"
+
+    def __init__(self, n_in: int, hidden: int = 64, max_batch: int = 1024, seed: int = 0):
+        h = _VP()
+        _check(lib().pvfl_mlp_create(n_in, hidden, max_batch, seed, ctypes.byref(h)))
+        super().__init__(h)
+        self.n_in, self.hidden = n_in, hidden
+        self.n_params = int(lib().pvfl_mlp_num_params(self.h))
+
+    def get_params(self):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(lib().pvfl_mlp_get_params(self.h, _ptr(out), _stream()))
+        return out
+
+    def set_params(self, p):
+        _check(lib().pvfl_mlp_set_params(self.h, _ptr(p), _stream()))
+
+    def _check_x(self, x, t=None):
+        import torch
+        if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous() or x.dim() != 2 \
+                or x.shape[1] != self.n_in:
+            raise ValueError(f"x must be a contiguous float32 device tensor of shape [batch, {self.n_in}]")
+        if t is not None and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()
+                              or t.shape != (x.shape[0],)):
+            raise ValueError("targets must be a contiguous float32 device vector of length batch")
+
+    def forward(self, x):
+        import torch
+        self._check_x(x)
+        y = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().pvfl_mlp_forward(self.h, _ptr(x), x.shape[0], _ptr(y), _stream()))
+        return y
+
+    def grad(self, x, t):
+        import torch
+        self._check_x(x, t)
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().pvfl_mlp_grad(self.h, _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss), _stream()))
+        return g, loss
+
+    def train_step(self, x, t, lr: float):
+        import torch
+        self._check_x(x, t)
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().pvfl_mlp_train_step(self.h, _ptr(x), _ptr(t), x.shape[0], lr, _ptr(loss), _stream()))
+        return loss

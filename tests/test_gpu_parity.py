@@ -5,6 +5,7 @@ import pytest
 
 from oracle import oracle as O
 from oracle import plans as PL
+from paper_2405_00482_amd import pvfl
 from paper_2405_00482_amd import workloads as W
 
 from gpu_util import context, dev_f64, dev_i64, dev_u64, export, export_ct, first_mismatch, host_u64
@@ -142,7 +143,7 @@ def test_rescale_matches_oracle(c1):
 # ---------------------------------------------------------------------------
 # the matrix product
 # ---------------------------------------------------------------------------
-def run_hybrid_both(name, X, y, lazy, kind="hybrid"):
+def run_hybrid_both(name, X, y, lazy, kind="hybrid", bsgs=0):
     prm = O.Params.from_dict(W.params_dict(name))
     ctx = context(name)
     N = prm.N
@@ -150,9 +151,10 @@ def run_hybrid_both(name, X, y, lazy, kind="hybrid"):
     sk_gpu = ctx.keygen(SEED_SK)
     s = O.keygen(prm, SEED_SK)
     if kind == "hybrid":
-        plan = ctx.plan(0, m, n, lazy=lazy)
+        plan = ctx.plan(0, m, n, lazy=lazy, bsgs=bsgs)
         oplan = PL.HybridPlan(m, n, prm.slots)
-        pts = PL.hybrid_pt_ints(prm, oplan, X, prm.scale)
+        pts = (PL.bsgs_pt_ints(prm, oplan, X, prm.scale, bsgs) if bsgs
+               else PL.hybrid_pt_ints(prm, oplan, X, prm.scale))
         cts_ints = PL.hybrid_ct_ints(prm, oplan, y, prm.scale)
     else:
         plan = ctx.plan(1, m, n, lazy=lazy, ras_in_ct=(kind == "diag_rot"))
@@ -178,7 +180,9 @@ def run_hybrid_both(name, X, y, lazy, kind="hybrid"):
     out = dev_f64(plan.bytes("ct_out") // 8)
     plan.matmul(ct, pt, keys, out)
     got = export_ct(ctx, lv, out, info["ct_out"])
-    if kind == "hybrid":
+    if kind == "hybrid" and bsgs:
+        want = PL.hybrid_matmul_bsgs(prm, oplan, octs, pts, okeys, bsgs)
+    elif kind == "hybrid":
         want = PL.hybrid_matmul(prm, oplan, octs, pts, okeys, lazy)
     else:
         want = [PL.diag_matmul(prm, oplan, octs[0], pts, okeys, lazy)]
@@ -204,6 +208,30 @@ def test_hybrid_partition_and_ragged(m, n):
     X = rng.uniform(-1, 1, (m, n))
     y = rng.uniform(-1, 1, n)
     run_hybrid_both("C1", X, y, True)
+
+
+@pytest.mark.parametrize("m,n,bs", [(64, 256, 2), (64, 256, 4), (100, 37, 2), (4096, 64, 8), (64, 4096, 4)])
+def test_bsgs_bit_exact(m, n, bs):
+    """baby-step/giant-step schedule: residues equal the oracle's, including
+    row and column partitions (several giant-step sums per output)"""
+    rng = np.random.default_rng(m * 7 + n)
+    X = rng.uniform(-1, 1, (m, n))
+    y = rng.uniform(-1, 1, n)
+    prm, s, outs, oplan = run_hybrid_both("C1", X, y, True, bsgs=bs)
+    zs = [O.decrypt_decode(prm, s, ct, prm.scale ** 2) for ct in outs]
+    got = PL.hybrid_lazy_ras(oplan, zs)
+    assert np.linalg.norm(got - X @ y) / np.linalg.norm(X @ y) < 2.0 ** -20
+
+
+def test_bsgs_rejects_bad_baby_steps():
+    ctx = context("C1")
+    for bs in (3, 1, 8):            # not a power of two; too small; m' = 8 needs bs <= 4
+        with pytest.raises(pvfl.PvflError):
+            ctx.plan(0, 64, 256, lazy=True, bsgs=bs)
+    with pytest.raises(pvfl.PvflError):
+        ctx.plan(0, 64, 256, lazy=False, bsgs=2)
+    with pytest.raises(pvfl.PvflError):
+        ctx.plan(1, 64, 16, lazy=True, bsgs=2)
 
 
 @pytest.mark.parametrize("kind,m,n", [("diag", 64, 16), ("diag", 16, 64), ("diag_rot", 16, 64)])

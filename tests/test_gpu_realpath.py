@@ -24,19 +24,20 @@ def signed_diff(a, b, q):
     return np.array([int(x) if x <= q // 2 else int(x) - q for x in d.ravel()], dtype=np.int64).reshape(a.shape)
 
 
-@pytest.mark.parametrize("name,m,n", [("C1", 16, 256), ("C2", 256, 1024), ("C1", 100, 37)])
-def test_encode_pt_within_one_of_oracle(name, m, n):
+@pytest.mark.parametrize("name,m,n,bs", [("C1", 16, 256, 0), ("C2", 256, 1024, 0), ("C1", 100, 37, 0),
+                                         ("C2", 256, 1024, 8)])
+def test_encode_pt_within_one_of_oracle(name, m, n, bs):
     prm = O.Params.from_dict(W.params_dict(name))
     ctx = context(name)
     rng = np.random.default_rng(m)
     X = rng.standard_normal((m, n))
-    plan = ctx.plan(0, m, n, lazy=True)
+    plan = ctx.plan(0, m, n, lazy=True, bsgs=bs)
     oplan = PL.HybridPlan(m, n, prm.slots)
     pt = dev_f64(plan.bytes("pt") // 8)
     plan.encode_pt(to_dev(X), pt)
     K = plan.info["pt_limbs"]
     got = export(ctx, prm.L, True, pt, plan.info["n_pts"])
-    want = PL.hybrid_pt_ints(prm, oplan, X, prm.scale)
+    want = PL.bsgs_pt_ints(prm, oplan, X, prm.scale, bs) if bs else PL.hybrid_pt_ints(prm, oplan, X, prm.scale)
     n_diff = 0
     for k, mk in enumerate(want):
         for l, q in enumerate(prm.qp(prm.L)):
@@ -71,13 +72,13 @@ def test_encrypt_real_matches_oracle():
         assert np.abs(signed_diff(got[0, l], want.c0[l], q)).max() <= 1
 
 
-@pytest.mark.parametrize("name,lazy", [("C1", True), ("C1", False), ("C2", True)])
-def test_hybrid_real_path_precision(name, lazy):
+@pytest.mark.parametrize("name,lazy,bs", [("C1", True, 0), ("C1", False, 0), ("C2", True, 0), ("C2", True, 8)])
+def test_hybrid_real_path_precision(name, lazy, bs):
     prm = O.Params.from_dict(W.params_dict(name))
     ctx = context(name)
     XT, r = W.c1_inputs() if name == "C1" else W.c2_inputs()
     m, n = XT.shape
-    plan = ctx.plan(0, m, n, lazy=lazy)
+    plan = ctx.plan(0, m, n, lazy=lazy, bsgs=bs)
     sk = ctx.keygen(5)
     keys = ctx.rotkeys(sk, plan.galois(), 6)
     pt = dev_f64(plan.bytes("pt") // 8)
@@ -91,7 +92,7 @@ def test_hybrid_real_path_precision(name, lazy):
     got = y.cpu().numpy()
     ref = XT @ r
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print(f"{name} lazy={lazy}: rel err 2^{np.log2(err):.2f}")
+    print(f"{name} lazy={lazy} bsgs={bs}: rel err 2^{np.log2(err):.2f}")
     assert err < (2.0 ** -20 if lazy else 2.0 ** -18)
 
 

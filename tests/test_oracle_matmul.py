@@ -118,3 +118,44 @@ def test_ctmat_plan(pack):
     outs = PL.ctmat_matmul(prm, plan, cts, pts)
     zs = [O.decrypt_decode(prm, s, c, prm.scale ** 2) for c in outs]
     assert rel_err(PL.ctmat_finish(plan, zs), A @ Wm) < 1e-3
+
+
+@pytest.mark.parametrize("m,n,S,bs", [(64, 64, 64, 2), (64, 64, 64, 8), (32, 128, 64, 4), (200, 300, 64, 2),
+                                      (16, 256, 64, 8)])
+def test_bsgs_reorder_is_exact_in_cleartext(m, n, S, bs):
+    """The baby-step/giant-step regrouping computes X y exactly as the
+    hoisted diagonal sum does (cleartext slots, FP64)."""
+    plan = PL.HybridPlan(m, n, S)
+    if not PL.bsgs_valid(plan, bs):
+        pytest.skip("m' too small for this baby step")
+    rng = np.random.default_rng(m + n + bs)
+    X = rng.uniform(-1, 1, (m, n))
+    y = rng.uniform(-1, 1, n)
+    got = PL.simulate_hybrid_bsgs(plan, X, y, bs)
+    assert np.allclose(got, X @ y, rtol=0, atol=1e-11)
+    assert np.allclose(got, PL.simulate_hybrid(plan, X, y), rtol=0, atol=1e-11)
+
+
+def test_bsgs_galois_set():
+    plan = PL.HybridPlan(64, 64, 64)      # m' = 64
+    gs = PL.bsgs_galois(plan, 128, 8)
+    want = {O.galois_rotl(k, 128) for k in range(1, 8)} | {O.galois_rotl(8 * j, 128) for j in range(1, 8)}
+    assert set(gs) == want and len(gs) == 14
+
+
+@pytest.mark.parametrize("m,n,bs", [(32, 32, 4), (64, 16, 2), (8, 64, 2)])
+def test_bsgs_encrypted(m, n, bs):
+    prm = tiny(6, 2, 1)
+    N = prm.N
+    plan = PL.HybridPlan(m, n, prm.slots)
+    assert PL.bsgs_valid(plan, bs)
+    rng = np.random.default_rng(9)
+    X = rng.uniform(-1, 1, (m, n))
+    y = rng.uniform(-1, 1, n)
+    s = O.keygen(prm, 11)
+    keys = {g: O.rotkey_gen(prm, s, g, 12) for g in PL.bsgs_galois(plan, N, bs)}
+    cts = [O.encrypt(prm, s, mm, prm.L, 13 + c) for c, mm in enumerate(PL.hybrid_ct_ints(prm, plan, y, prm.scale))]
+    pts = PL.bsgs_pt_ints(prm, plan, X, prm.scale, bs)
+    outs = PL.hybrid_matmul_bsgs(prm, plan, cts, pts, keys, bs)
+    zs = [O.decrypt_decode(prm, s, ct, prm.scale * prm.scale) for ct in outs]
+    assert rel_err(PL.hybrid_lazy_ras(plan, zs), X @ y) < 1e-3
