@@ -102,9 +102,10 @@ def main():
     ap.add_argument("--cpu-diagonals", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--group", type=int, default=2)
-    ap.add_argument("--vec", type=int, default=1)
-    ap.add_argument("--chunk", type=int, default=32)
+    ap.add_argument("--group", type=int, default=None, help="default: the tuner database's choice, else 2")
+    ap.add_argument("--vec", type=int, default=None, help="default: the tuner database's choice, else 1")
+    ap.add_argument("--chunk", type=int, default=None, help="default: the tuner database's choice, else 32")
+    ap.add_argument("--chunk-major", type=int, default=None, help="default: the tuner database's choice, else 1")
     ap.add_argument("--percall-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (for scaling the HBM byte counters)")
@@ -150,8 +151,18 @@ def main():
     pt_gib = sum(t.numel() for t in pts) * 8 / 2 ** 30
     log(f"[bench] {macs} cleartext MACs per step, {pt_gib:.2f} GiB of plaintexts")
 
+    from paper_2405_00482_amd import tune
+    tuned = tune.lookup(tune.signature(name, shapes))
+    topts = tuned["opts"] if tuned else {"group": 2, "chunk": 32, "vec": 1, "chunk_major": 1}
+    for k in ("group", "chunk", "vec", "chunk_major"):
+        if getattr(args, k) is None:
+            setattr(args, k, topts[k])
+    from_db = tuned is not None and all(getattr(args, k) == tuned["opts"][k]
+                                       for k in ("group", "chunk", "vec", "chunk_major"))
+    log(f"[bench] launch options group {args.group}, chunk {args.chunk}, vec {args.vec}, chunk_major "
+        f"{args.chunk_major}{' (tuner database)' if from_db else ''}")
     batch = pvfl.Batch(ctx, plans, X=Xs, v=rs, pt=pts, ct=cts, out=outs, y=ys, keys=keys,
-                       group=args.group, chunk=args.chunk, vec=args.vec)
+                       group=args.group, chunk=args.chunk, vec=args.vec, chunk_major=bool(args.chunk_major))
     binfo = batch.info()
     log(f"[bench] batch: {binfo['work_items']} work items, key stream {binfo['key_bytes'] / 2 ** 30:.2f} GiB, "
         f"plaintexts {binfo['pt_bytes'] / 2 ** 30:.2f} GiB")
@@ -208,7 +219,8 @@ def main():
     dom = max(kt, key=lambda k: kt[k]["total_ms"])
     dk = kt[dom]
     achieved = dk["bytes"] / (dk["total_ms"] * 1e-3) / 1e9 if dk["total_ms"] > 0 else 0.0
-    launch_key = f"C3 x{len(shapes)}, group {args.group}, chunk {args.chunk}, vec {args.vec}"
+    launch_key = f"C3 x{len(shapes)}, group {args.group}, chunk {args.chunk}, vec {args.vec}" + \
+        ("" if args.chunk_major else ", slot-major")
     traffic = measured_traffic(launch_key, KERNEL_SYMBOL[dom])
     ms_percall = None
     if args.percall_steps > 0:
@@ -230,7 +242,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"C3: {len(shapes)} products X^T[[r]], batch logU[512,4096], features logU[32,2000], "
                                f"N=2^14, 4+1 primes, Delta=2^40, hybrid plan, lazy ModDown, batched form "
-                               f"(group {args.group}, chunk {args.chunk}, vec {args.vec}){'' if args.no_graph else ', HIP graph'}",
+                               f"(group {args.group}, chunk {args.chunk}, vec {args.vec}, chunk_major "
+                               f"{args.chunk_major}{', autotuned' if from_db else ''})"
+                               f"{'' if args.no_graph else ', HIP graph'}",
                    "macs_per_step": macs, "max_rel_err": max(errs),
                    "percall_ms_per_step": ms_percall, "instrumented_ms_per_step": ms_instrumented},
         "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,

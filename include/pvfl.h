@@ -259,6 +259,36 @@ pvfl_status pvfl_mlp_train_step(pvfl_mlp* mlp, const float* x_dev, const float* 
                                 float* loss_dev, void* stream);
 void pvfl_mlp_destroy(pvfl_mlp* mlp);
 
+/* Plan selection.  For X (m x n) times an encrypted vector at `level`, the
+ * candidates are every valid HYBRID / DIAG / ROW plan with lazy or
+ * per-rotation ModDown and every baby-step size (Sec. 3-4; Tables 2 and 3
+ * give their operation counts).
+ * pvfl_plan_candidates: writes up to cap option sets, *count = how many exist.
+ * pvfl_plan_features: the PVFL_PLAN_FEATURES-long feature vector of a plan
+ *   (log2 N, l+1, alpha, beta, K, log2 m, log2 n, log2 m', kind one-hot, lazy,
+ *   in-ciphertext RaS, BSGS flag and log2 b, log2(1+count) of Mult, Add, Rot,
+ *   HstRot, ModUp, ModDown, encoded limbs, keys, blocks).
+ * pvfl_plan_analytic_ms: sum over the PVFL_COST_TERMS counts (Mult, Add, Rot,
+ *   HstRot, ModUp, ModDown, encoded plaintext limbs, 1) of count x costs[i].
+ * pvfl_planner_create: a learned latency model -- a pvfl_mlp over features
+ *   standardised by (x - x_mean) / x_std predicting (ln ms - y_mean) / y_std.
+ *   The network is borrowed and must outlive the planner.
+ * pvfl_plan_choose: the candidate of least predicted latency, by the network
+ *   when costs is NULL, else by the analytic model.  Synchronises `stream`. */
+#define PVFL_PLAN_FEATURES 24
+#define PVFL_COST_TERMS 8
+typedef struct pvfl_planner pvfl_planner;
+pvfl_status pvfl_plan_candidates(pvfl_ctx* ctx, int32_t m, int32_t n, int32_t level, pvfl_plan_opts* out, int32_t cap,
+                                 int32_t* count);
+int32_t pvfl_plan_num_features(void);
+pvfl_status pvfl_plan_features(const pvfl_plan* plan, float* out, int32_t cap);
+pvfl_status pvfl_plan_analytic_ms(const pvfl_plan* plan, const double* costs, double* ms);
+pvfl_status pvfl_planner_create(pvfl_mlp* mlp, const float* x_mean, const float* x_std, float y_mean, float y_std,
+                                pvfl_planner** out);
+pvfl_status pvfl_plan_choose(pvfl_planner* planner, pvfl_ctx* ctx, int32_t m, int32_t n, int32_t level,
+                             const double* costs, pvfl_plan_opts* chosen, double* predicted_ms, void* stream);
+void pvfl_planner_destroy(pvfl_planner* planner);
+
 /* Optional kernel timing for measurement.  When enabled, every launch of the
  * timed kernel classes is bracketed by HIP events recorded on the launch's
  * stream; pvfl_timing_read waits for the recorded events of one class, returns

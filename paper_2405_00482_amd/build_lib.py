@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpvfl.so")
 SOURCES = ["he_kernels.hip", "encode_kernels.hip", "batch.hip", "mlp.hip", "capi.cpp", "plan.cpp", "codec.cpp",
-           "batch.cpp", "mlp_capi.cpp"]
+           "batch.cpp", "mlp_capi.cpp", "planner.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
 

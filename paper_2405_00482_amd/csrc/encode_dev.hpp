@@ -23,30 +23,66 @@ __device__ __forceinline__ double round_half_away(double x) {
   return r;
 }
 
-// In-place DIF FFT over M = N/2 points in LDS, sign -1 (conj = false) or +1.
+// S radix-2 DIF stages s0 .. s0+S-1 of the M = N/2 point FFT, on register
+// sets of 2^S elements {base + u * stride} (stride = half-length of the last
+// stage).  Each thread owns 8 elements (M = 8 T), i.e. 8 / 2^S sets; the sets
+// partition the array, so a set is loaded, transformed and written back in
+// place without a barrier in between.  At stage s a butterfly pairs elements
+// half_s = M >> (s+1) apart with twiddle W_M^(j 2^s), j = index mod half_s,
+// which for element u of a set is off + (u mod 2^(S-1-st)) * stride.
+template <int LOGN, int S>
+__device__ __forceinline__ void fft_pass(double2* a, int s0, const double2* __restrict__ tw, bool conj) {
+  constexpr int LOGM = LOGN - 1, M = 1 << LOGM, T = NttShape<LOGN>::T;
+  constexpr int SET = 1 << S, NS = 8 >> S;
+  static_assert(M == 8 * T, "eight FFT points per thread");
+  const int stride = M >> (s0 + S);
+  const int tid = threadIdx.x;
+  int base[NS], off[NS];
+  double2 x[8];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int c = q * T + tid;
+    off[q] = c % stride;
+    base[q] = (c / stride) * (stride << S) + off[q];
+#pragma unroll
+    for (int u = 0; u < SET; ++u) x[q * SET + u] = a[cpad(base[q] + u * stride)];
+  }
+#pragma unroll
+  for (int st = 0; st < S; ++st) {
+    const int s = s0 + st;
+    const int hs = SET >> (st + 1);
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+#pragma unroll
+      for (int u = 0; u < SET; ++u) {
+        if (u & hs) continue;
+        double2 w = tw[(off[q] + (u & (hs - 1)) * stride) << s];
+        if (conj) w = cconj(w);
+        const double2 U = x[q * SET + u], V = x[q * SET + u + hs];
+        x[q * SET + u] = make_double2(U.x + V.x, U.y + V.y);
+        x[q * SET + u + hs] = cmul(make_double2(U.x - V.x, U.y - V.y), w);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NS; ++q)
+#pragma unroll
+    for (int u = 0; u < SET; ++u) a[cpad(base[q] + u * stride)] = x[q * SET + u];
+  __syncthreads();
+}
+
+// In-place DIF FFT over M = N/2 points in LDS (padded by cpad), sign -1
+// (conj = false) or +1; the result is left in bit-reversed order.  The input
+// must be complete in LDS (barrier before the call); the call ends with a
+// barrier.  Radix-8 register passes: ceil(log2(M) / 3) LDS round trips.
 template <int LOGN>
 __device__ __forceinline__ void fft_dif_lds(double2* a, const double2* __restrict__ tw, bool conj) {
-  constexpr int LOGM = LOGN - 1, M = 1 << LOGM;
-  constexpr int T = NttShape<LOGN>::T;
-  constexpr int BF = M / 2 / T;  // 4
-  const int tid = threadIdx.x;
+  constexpr int LOGM = LOGN - 1;
+  int s0 = 0;
 #pragma unroll 1
-  for (int s = 0; s < LOGM; ++s) {
-    const int lhalf = LOGM - 1 - s;   // log2 of half the current length
-    const int half = 1 << lhalf;
-#pragma unroll
-    for (int r = 0; r < BF; ++r) {
-      const int b = tid + r * T;
-      const int blk = b >> lhalf, j = b & (half - 1);
-      const int i0 = (blk << (lhalf + 1)) + j, i1 = i0 + half;
-      double2 w = tw[j << s];  // W_len^j = W_M^(j M/len)
-      if (conj) w = cconj(w);
-      const double2 u = a[cpad(i0)], v = a[cpad(i1)];
-      a[cpad(i0)] = make_double2(u.x + v.x, u.y + v.y);
-      a[cpad(i1)] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
-    }
-    __syncthreads();
-  }
+  for (; s0 + 3 <= LOGM; s0 += 3) fft_pass<LOGN, 3>(a, s0, tw, conj);
+  if (LOGM - s0 == 2) fft_pass<LOGN, 2>(a, s0, tw, conj);
+  if (LOGM - s0 == 1) fft_pass<LOGN, 1>(a, s0, tw, conj);
 }
 
 __device__ __forceinline__ int brev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }

@@ -121,7 +121,7 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
         I.n_rot = 0;
         I.n_hstrot = (int64_t)I.col_blocks * (I.mprime - 1);
         I.n_modup = I.mprime > 1 ? I.col_blocks : 0;
-        I.n_moddown = lazy ? I.row_blocks : (int)I.n_hstrot * I.row_blocks;
+        I.n_moddown = lazy ? (I.mprime > 1 ? I.row_blocks : 0) : (int)I.n_hstrot * I.row_blocks;
       }
       break;
     }
@@ -148,7 +148,7 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
       I.n_add = nd - 1 + I.n_rot;
       I.n_hstrot = nd - 1;
       I.n_modup = (nd > 1 ? 1 : 0) + (int)I.n_rot;
-      I.n_moddown = (lazy ? 1 : nd - 1) + (int)I.n_rot;
+      I.n_moddown = (lazy ? (nd > 1 ? 1 : 0) : nd - 1) + (int)I.n_rot;
       break;
     }
     case PVFL_PLAN_ROW: {
@@ -321,6 +321,19 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
   double* rct = v + (bs ? 2 * Q : 0);                   // BSGS: phi(c0) [lv+1][N]
   LaunchCtx L = launch_ctx(c, stream);
   const int mprime = p->info.mprime;
+  if (mprime == 1) {
+    // no rotation: ModDown(P * c * pt) is c * pt exactly, so skip Q u P
+    // (the Q limbs of a Q u P plaintext come first)
+    for (int b = 0; b < RB; ++b) {
+      double* ob = out + (size_t)b * 2 * Q;
+      HIP_TRY(launch_fill_zero(L, ob, 2 * Q));
+      for (int cb = 0; cb < CB; ++cb) {
+        const double* ct = ct_in + (size_t)cb * 2 * Q;
+        HIP_TRY(launch_eager_term(L, ct, ct + Q, nullptr, 0, pts + (size_t)(b * CB + cb) * KN, lv, N, ob));
+      }
+    }
+    return PVFL_OK;
+  }
   // one ModUp and one P*c per input ciphertext, shared by every row block
   for (int cb = 0; cb < CB; ++cb) {
     const double* ct = ct_in + (size_t)cb * 2 * Q;

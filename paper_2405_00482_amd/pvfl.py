@@ -35,6 +35,11 @@ class Params(ctypes.Structure):
                 ("log2_scale", ctypes.c_double)]
 
 
+PLAN_FEATURES = 24
+COST_TERMS = 8
+COST_NAMES = ("mult", "add", "rot", "hstrot", "modup", "moddown", "pt_limbs", "const")
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("n_out", ctypes.c_int32),
                 ("level", ctypes.c_int32), ("lazy_moddown", ctypes.c_int32), ("ras_in_ct", ctypes.c_int32),
@@ -97,6 +102,13 @@ def lib():
             "pvfl_decrypt_decode": [_VP, _VP, _VP, _VP, _VP],
             "pvfl_timing_enable": [_VP, i32],
             "pvfl_mlp_create": [i32, i32, i32, u64, ctypes.POINTER(_VP)],
+            "pvfl_plan_candidates": [_VP, i32, i32, i32, ctypes.POINTER(PlanOpts), i32, ctypes.POINTER(i32)],
+            "pvfl_plan_features": [_VP, ctypes.POINTER(ctypes.c_float), i32],
+            "pvfl_plan_analytic_ms": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+            "pvfl_planner_create": [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                    ctypes.c_float, ctypes.c_float, ctypes.POINTER(_VP)],
+            "pvfl_plan_choose": [_VP, _VP, i32, i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PlanOpts),
+                                 ctypes.POINTER(ctypes.c_double), _VP],
             "pvfl_mlp_get_params": [_VP, _VP, _VP],
             "pvfl_mlp_set_params": [_VP, _VP, _VP],
             "pvfl_mlp_forward": [_VP, _VP, i32, _VP, _VP],
@@ -125,8 +137,10 @@ def lib():
             f.restype = sz
         L.pvfl_mlp_num_params.argtypes = [_VP]
         L.pvfl_mlp_num_params.restype = i32
+        L.pvfl_plan_num_features.argtypes = []
+        L.pvfl_plan_num_features.restype = i32
         for name in ("pvfl_context_destroy", "pvfl_sk_destroy", "pvfl_rotkeys_destroy", "pvfl_plan_destroy",
-                     "pvfl_batch_destroy", "pvfl_mlp_destroy"):
+                     "pvfl_batch_destroy", "pvfl_mlp_destroy", "pvfl_planner_destroy"):
             f = getattr(L, name)
             f.argtypes = [_VP]
             f.restype = None
@@ -204,6 +218,19 @@ class Context(_Handle):
         h = _VP()
         _check(lib().pvfl_rotkeys_gen(self.h, sk.h, arr, len(g), seed, ctypes.byref(h)))
         return RotKeys(h, list(g), keep=(self,))
+
+    def candidates(self, m: int, n: int, level: int = -1) -> list:
+        """every valid plan option set for X (m x n) times an encrypted vector"""
+        cap = 64
+        arr = (PlanOpts * cap)()
+        cnt = ctypes.c_int32()
+        _check(lib().pvfl_plan_candidates(self.h, m, n, level, arr, cap, ctypes.byref(cnt)))
+        return [opts_dict(arr[i]) for i in range(cnt.value)]
+
+    def plan_from(self, o: dict) -> "Plan":
+        return self.plan(o["kind"], o["m"], o["n"], n_out=o.get("n_out", 0), level=o.get("level", -1),
+                         lazy=bool(o.get("lazy_moddown", 1)), ras_in_ct=bool(o.get("ras_in_ct", 0)),
+                         pack=o.get("pack", 1), pt_log2_scale=o.get("pt_log2_scale", 0.0), bsgs=o.get("bsgs", 0))
 
     def plan(self, kind: int, m: int, n: int, n_out: int = 0, level: int = -1, lazy: bool = True,
              ras_in_ct: bool = False, pack: int = 1, pt_log2_scale: float = 0.0, bsgs: int = 0) -> "Plan":
@@ -296,10 +323,54 @@ class Plan(_Handle):
     def decrypt_decode(self, sk, ct, out):
         _check(lib().pvfl_decrypt_decode(self.h, sk.h, _ptr(ct), _ptr(out), _stream()))
 
+    def features(self) -> list:
+        arr = (ctypes.c_float * PLAN_FEATURES)()
+        _check(lib().pvfl_plan_features(self.h, arr, PLAN_FEATURES))
+        return [float(x) for x in arr]
+
+    def analytic_ms(self, costs) -> float:
+        c = (ctypes.c_double * COST_TERMS)(*costs)
+        out = ctypes.c_double()
+        _check(lib().pvfl_plan_analytic_ms(self.h, c, ctypes.byref(out)))
+        return out.value
+
     def matmul(self, ct, pt, keys, out, ws=None):
         ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
         _check(lib().pvfl_matmul_ct_pt(self.h, _ptr(ct), _ptr(pt), keys.h if keys is not None else None, _ptr(out),
                                        _ptr(ws), ws_bytes, _stream()))
+
+
+def choose_analytic(ctx: Context, m: int, n: int, costs, level: int = -1):
+    """the candidate of least analytic latency (no network needed)"""
+    c = (ctypes.c_double * COST_TERMS)(*costs)
+    o = PlanOpts()
+    pred = ctypes.c_double()
+    _check(lib().pvfl_plan_choose(None, ctx.h, m, n, level, c, ctypes.byref(o), ctypes.byref(pred), _stream()))
+    return opts_dict(o), pred.value
+
+
+def opts_dict(o: PlanOpts) -> dict:
+    return {name: getattr(o, name) for name, _ in o._fields_}
+
+
+class Planner(_Handle):
+    """Native plan selection: the latency network (or, with costs, the
+    analytic operation-count model) ranks every candidate plan."""
+    _destroy = "pvfl_planner_destroy"
+
+    def __init__(self, mlp: "Mlp", x_mean, x_std, y_mean: float, y_std: float):
+        xm = (ctypes.c_float * PLAN_FEATURES)(*x_mean)
+        xs = (ctypes.c_float * PLAN_FEATURES)(*x_std)
+        h = _VP()
+        _check(lib().pvfl_planner_create(mlp.h if mlp is not None else None, xm, xs, y_mean, y_std, ctypes.byref(h)))
+        super().__init__(h, keep=(mlp,))
+
+    def choose(self, ctx: Context, m: int, n: int, level: int = -1, costs=None):
+        c = (ctypes.c_double * COST_TERMS)(*costs) if costs is not None else None
+        o = PlanOpts()
+        pred = ctypes.c_double()
+        _check(lib().pvfl_plan_choose(self.h, ctx.h, m, n, level, c, ctypes.byref(o), ctypes.byref(pred), _stream()))
+        return opts_dict(o), pred.value
 
 
 def _ptr_array(items):

@@ -91,3 +91,20 @@ def seeds(name: str) -> dict:
     """Seeds of the counter-based generator for keys and encryption noise."""
     s = seed_of(name)
     return {"sk": s * 7919 + 1, "rotkeys": s * 7919 + 2, "enc": s * 7919 + 3}
+
+
+def planner_shapes(name: str, count: int):
+    """Shapes (m, n) for plan-selection data: m ~ logU[1, 2048] rows of X,
+    n ~ logU[2, 4096] entries of the encrypted vector (the feature and batch
+    ranges of the VFL products, extended down to tiny shapes)."""
+    g = rng(name, 7)
+    m = np.exp(g.uniform(np.log(1), np.log(2048), size=count)).astype(np.int64)
+    n = np.exp(g.uniform(np.log(2), np.log(4096), size=count)).astype(np.int64)
+    return [(int(max(1, a)), int(max(2, b))) for a, b in zip(m, n)]
+
+
+def planner_inputs(name: str, idx: int, shape):
+    """X ~ N(0,1) (m x n) and y ~ U[-1,1] (n) for planner shape idx"""
+    g = rng(name, 1000 + idx)
+    m, n = shape
+    return g.standard_normal(size=(m, n)), g.uniform(-1.0, 1.0, size=n)

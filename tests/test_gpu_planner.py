@@ -1,0 +1,99 @@
+"""Plan selection on the GPU: candidate enumeration and counts, the learned
+latency model against exhaustive tuning (regret on held-out shapes), and the
+native choice path.  The exhaustive timings are the committed measurement
+database of every candidate plan on an MI355X."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import plans as PL
+from paper_2405_00482_amd import planner as P
+from paper_2405_00482_amd import pvfl
+from paper_2405_00482_amd import workloads as W
+
+from gpu_util import context, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def db():
+    if not os.path.exists(P.DEFAULT_DB):
+        pytest.skip("no plan-latency database")
+    with open(P.DEFAULT_DB) as f:
+        return json.load(f)["records"]
+
+
+@pytest.fixture(scope="module")
+def trained(db):
+    res, net, st = P.evaluate(db, log=print)
+    return res, net, st
+
+
+@pytest.mark.parametrize("m,n", [(16, 256), (100, 37), (1, 2), (2000, 3000)])
+def test_candidates_and_table2_counts(m, n):
+    ctx = context("C2")
+    cands = ctx.candidates(m, n)
+    kinds = [(o["kind"], o["lazy_moddown"], o["bsgs"]) for o in cands]
+    assert kinds[0] == (0, 1, 0) and (0, 0, 0) in kinds
+    p = ctx.plan_from(cands[0])
+    f = p.features()
+    assert len(f) == pvfl.PLAN_FEATURES and f[0] == 13
+    oc = PL.HybridPlan(m, n, ctx.N // 2).op_counts()
+    info = p.info
+    assert (info["n_add"], info["n_mult"], info["n_rot"], info["n_hstrot"]) == \
+        (oc["add"], oc["mult"], oc["rot"], oc["hstrot"])
+    for o in cands:
+        if o["bsgs"]:
+            q = ctx.plan_from(o).info
+            mp = q["mprime"]
+            b = o["bsgs"]
+            assert q["n_hstrot"] == q["col_blocks"] * (b - 1)
+            assert q["n_rot"] == q["row_blocks"] * q["col_blocks"] * (mp // b - 1)
+
+
+def test_learned_planner_regret_within_ten_percent(trained):
+    res, _, _ = trained
+    mlp, ana, dflt = res["mlp"], res["analytic"], res["paper_default"]
+    print(f"held-out regret: network mean {mlp['mean']:.4f} max {mlp['max']:.4f}; analytic mean "
+          f"{ana['mean']:.4f} max {ana['max']:.4f}; always-hybrid-lazy mean {dflt['mean']:.4f}")
+    assert mlp["mean"] <= 0.10
+    # the network must not do worse than the operation-count model it replaces
+    assert mlp["mean"] <= ana["mean"] + 1e-9
+
+
+def test_native_choice_agrees_with_network(db, trained):
+    res, net, st = trained
+    _, test = P.split(db)
+    planner = pvfl.Planner(net, st.x_mean, st.x_std, st.y_mean, st.y_std)
+    seen = 0
+    for cfg in ("C1", "C2"):
+        ctx = context(cfg)
+        shapes = sorted(set((r["idx"], r["m"], r["n"]) for r in test if r["config"] == cfg))[:6]
+        for idx, m, n in shapes:
+            rows = [r for r in test if r["config"] == cfg and r["idx"] == idx]
+            pred = P.mlp_predict_ms(net, st, rows)
+            got, ms = planner.choose(ctx, m, n)
+            k = [i for i, r in enumerate(rows) if {q: got[q] for q in r["opts"]} == r["opts"]]
+            assert len(k) == 1, (cfg, m, n, got)
+            # the native pick is the network's minimum (up to FP32 standardisation rounding)
+            assert pred[k[0]] <= float(np.min(pred)) * (1 + 1e-4), (cfg, m, n)
+            assert abs(ms / float(np.min(pred)) - 1) < 1e-3
+            seen += 1
+    assert seen >= 8
+
+
+def test_native_analytic_choice_agrees(db, trained):
+    res, _, _ = trained
+    _, test = P.split(db)
+    ctx = context("C2")
+    costs = res["costs"]["C2"]
+    for idx, m, n in sorted(set((r["idx"], r["m"], r["n"]) for r in test if r["config"] == "C2"))[:6]:
+        rows = [r for r in test if r["config"] == "C2" and r["idx"] == idx]
+        pred = P.analytic_predict_ms(res["costs"], rows)
+        got, ms = pvfl.choose_analytic(ctx, m, n, costs)
+        assert abs(ms - float(np.min(pred))) <= 1e-9 * max(1.0, ms)
+        best = [r["opts"] for r, p in zip(rows, pred) if abs(p - np.min(pred)) <= 1e-12 * max(1.0, p)]
+        assert any({k: got[k] for k in o} == o for o in best)
