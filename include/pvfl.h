@@ -31,7 +31,7 @@
  *   (c0 then c1).  Basis order: q_0..q_l, then the special primes p_0..p_{a-1}.
  *   Use pvfl_export_coeffs to read residues back as canonical uint64
  *   coefficient-domain values.
- * - All primes must be below 2^49 and congruent to 1 mod 2N.
+ * - All primes must be below 2^48 and congruent to 1 mod 2N.
  */
 #ifndef PVFL_H
 #define PVFL_H

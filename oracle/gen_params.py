@@ -2,7 +2,7 @@
 
 Run:  python -m oracle.gen_params   (writes paper_2405_00482_amd/params.json)
 
-Primes are NTT-friendly (q = 1 mod 2N) and below 2^49, which the library's
+Primes are NTT-friendly (q = 1 mod 2N) and below 2^48, which the library's
 exact binary64 modular arithmetic requires.  Rule: ciphertext primes are the
 largest such primes below 2^40 (C1 uses two of them, as its workload states
 "~40-bit"); for the larger rings q_0 and the special primes are the largest

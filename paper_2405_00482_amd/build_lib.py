@@ -14,7 +14,8 @@ OUT = os.path.join(HERE, "libpvfl.so")
 SOURCES = ["he_kernels.hip", "encode_kernels.hip", "batch.hip", "mlp.hip", "capi.cpp", "plan.cpp", "codec.cpp",
            "batch.cpp", "mlp_capi.cpp", "planner.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result",
+         "-Werror=return-type", "-Werror=uninitialized"]
 
 
 def build(verbose: bool = False) -> str:

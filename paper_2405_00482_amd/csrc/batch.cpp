@@ -54,10 +54,10 @@ struct pvfl_batch {
   hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
   bool has_X = false, has_v = false, has_y = false;
   ~pvfl_batch() {
-    if (graph_exec) hipGraphExecDestroy(graph_exec);
-    if (graph) hipGraphDestroy(graph);
-    if (cap_stream) hipStreamDestroy(cap_stream);
-    for (void* p : allocs) hipFree(p);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (void* p : allocs) (void)hipFree(p);
   }
 };
 
@@ -352,8 +352,8 @@ extern "C" pvfl_status pvfl_batch_run(pvfl_batch* b, const pvfl_sk* sk, uint64_t
   if (!use_graph) return run_phases(b, sk, seed, stream);
   if (!b->has_X || !b->has_v || !b->has_y) return fail(PVFL_E_INVALID, "batch was created without input/output buffers");
   if (!b->graph_exec || b->graph_sk != sk || b->graph_seed != seed) {
-    if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->graph_exec = nullptr;
     b->graph = nullptr;
     pvfl_status st = enc_tables_for(b->ctx, nullptr, nullptr);  // tables are created outside the capture
@@ -367,7 +367,7 @@ extern "C" pvfl_status pvfl_batch_run(pvfl_batch* b, const pvfl_sk* sk, uint64_t
     const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     b->ctx->timing_on = timing;
     if (st != PVFL_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return st;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");

@@ -267,20 +267,25 @@ static hipError_t diag_batch_pgv(const LaunchCtx& L, const BatchDiagArgs& a, int
 
 // dynamic LDS above the default limit must be opted in per kernel instance
 template <int PG, int V>
-static void diag_batch_allow_lds() {
+static hipError_t diag_batch_allow_lds() {
   const int bytes = 160 * 1024;
-  hipFuncSetAttribute((const void*)k_diag_batch<PG, 1, V>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  hipFuncSetAttribute((const void*)k_diag_batch<PG, 2, V>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  hipFuncSetAttribute((const void*)k_diag_batch<PG, 3, V>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  hipFuncSetAttribute((const void*)k_diag_batch<PG, 4, V>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* fn[4] = {(const void*)k_diag_batch<PG, 1, V>, (const void*)k_diag_batch<PG, 2, V>,
+                       (const void*)k_diag_batch<PG, 3, V>, (const void*)k_diag_batch<PG, 4, V>};
+  for (const void* f : fn) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_diag_batch(const LaunchCtx& L, const BatchDiagArgs& a, int pg, int beta, int vec) {
   if (a.n_tasks <= 0) return hipSuccess;
   static bool lds_opt_in = false;
   if (!lds_opt_in) {
-    diag_batch_allow_lds<1, 1>(); diag_batch_allow_lds<2, 1>(); diag_batch_allow_lds<4, 1>();
-    diag_batch_allow_lds<1, 2>(); diag_batch_allow_lds<2, 2>(); diag_batch_allow_lds<4, 2>();
+    const hipError_t e[6] = {diag_batch_allow_lds<1, 1>(), diag_batch_allow_lds<2, 1>(), diag_batch_allow_lds<4, 1>(),
+                             diag_batch_allow_lds<1, 2>(), diag_batch_allow_lds<2, 2>(), diag_batch_allow_lds<4, 2>()};
+    for (hipError_t x : e)
+      if (x != hipSuccess) return x;
     lds_opt_in = true;
   }
   if (a.N % (256 * vec) != 0) return hipErrorInvalidValue;

@@ -26,7 +26,8 @@ pvfl_status fail(pvfl_status s, const std::string& msg) {
   return s;
 }
 pvfl_status hip_fail(hipError_t e, const char* where) {
-  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  g_err = std::string(where) + ": " + hipGetErrorName(e) + " (" + std::to_string((int)e) + "): " +
+          hipGetErrorString(e);
   return PVFL_E_DEVICE;
 }
 }  // namespace pvfl
@@ -95,12 +96,12 @@ static int bit_reverse(int x, int bits) {
 // ---------------------------------------------------------------------------
 pvfl_ctx::~pvfl_ctx() {
   for (auto& t : timed) {
-    hipEventDestroy(t.start);
-    hipEventDestroy(t.stop);
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
   }
   if (enc_tabs && enc_tabs_free) enc_tabs_free(enc_tabs);
-  if (scratch) hipFree(scratch);
-  for (void* p : dev_allocs) hipFree(p);
+  if (scratch) (void)hipFree(scratch);
+  for (void* p : dev_allocs) (void)hipFree(p);
 }
 
 static pvfl_status dev_upload(pvfl_ctx* c, const void* host, size_t bytes, void** out) {
@@ -220,8 +221,8 @@ extern "C" pvfl_status pvfl_context_create(const pvfl_params* prm, int device, p
   for (uint32_t i = 0; i < prm->n_p; ++i) c->primes.push_back(prm->p[i]);
   for (size_t i = 0; i < c->primes.size(); ++i) {
     const u64 q = c->primes[i];
-    if (q >= (1ull << 49) || q < 3 || (q - 1) % (2 * (u64)N) != 0 || !probable_prime(q))
-      return fail(PVFL_E_INVALID, "prime " + std::to_string(i) + " is not an NTT-friendly prime below 2^49");
+    if (q >= (1ull << 48) || q < 3 || (q - 1) % (2 * (u64)N) != 0 || !probable_prime(q))
+      return fail(PVFL_E_INVALID, "prime " + std::to_string(i) + " is not an NTT-friendly prime below 2^48");
     for (size_t k = 0; k < i; ++k)
       if (c->primes[k] == q) return fail(PVFL_E_INVALID, "primes must be distinct");
   }
@@ -306,11 +307,11 @@ extern "C" void pvfl_context_destroy(pvfl_ctx* c) { delete c; }
 // keys
 // ---------------------------------------------------------------------------
 pvfl_sk::~pvfl_sk() {
-  if (s) hipFree(s);
+  if (s) (void)hipFree(s);
 }
 pvfl_rotkeys::~pvfl_rotkeys() {
-  if (keys) hipFree(keys);
-  if (slot_of_rot_dev) hipFree(slot_of_rot_dev);
+  if (keys) (void)hipFree(keys);
+  if (slot_of_rot_dev) (void)hipFree(slot_of_rot_dev);
 }
 
 extern "C" pvfl_status pvfl_keygen(pvfl_ctx* c, uint64_t seed, pvfl_sk** out) {
@@ -379,8 +380,8 @@ extern "C" pvfl_status pvfl_rotkeys_gen(pvfl_ctx* c, const pvfl_sk* sk, const ui
     }
   }
   HIP_TRY(hipDeviceSynchronize());
-  if (d_rot) hipFree(d_rot);
-  if (d_gal) hipFree(d_gal);
+  if (d_rot) (void)hipFree(d_rot);
+  if (d_gal) (void)hipFree(d_gal);
   *out = rk.release();
   return PVFL_OK;
 }
@@ -449,7 +450,7 @@ namespace pvfl {
 // per-context scratch for single operations (grown on demand, stream-ordered use)
 pvfl_status ctx_scratch(pvfl_ctx* c, size_t bytes, double** out) {
   if (c->scratch_bytes < bytes) {
-    if (c->scratch) hipFree(c->scratch);
+    if (c->scratch) (void)hipFree(c->scratch);
     c->scratch = nullptr;
     c->scratch_bytes = 0;
     if (hipMalloc((void**)&c->scratch, bytes) != hipSuccess) return fail(PVFL_E_NOMEM, "scratch allocation");
@@ -559,8 +560,8 @@ extern "C" pvfl_status pvfl_timing_read(pvfl_ctx* c, int32_t cls, double* total_
     ms += e;
     by += t.bytes;
     ++n;
-    hipEventDestroy(t.start);
-    hipEventDestroy(t.stop);
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
   }
   c->timed.swap(keep);
   *total_ms = ms;

@@ -102,16 +102,16 @@ struct KernelTimer {
   double bytes;
   hipEvent_t a = nullptr;
   KernelTimer(pvfl_ctx* c_, void* stream, int cls_, double bytes_) : c(c_), s((hipStream_t)stream), cls(cls_), bytes(bytes_) {
-    if (c->timing_on && hipEventCreate(&a) == hipSuccess) hipEventRecord(a, s);
+    if (c->timing_on && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
   }
   void stop() {
     if (!a) return;
     hipEvent_t b;
     if (hipEventCreate(&b) == hipSuccess) {
-      hipEventRecord(b, s);
+      (void)hipEventRecord(b, s);
       c->timed.push_back(pvfl_ctx::Timed{a, b, cls, bytes});
     } else {
-      hipEventDestroy(a);
+      (void)hipEventDestroy(a);
     }
     a = nullptr;
   }

@@ -23,7 +23,7 @@ struct EncHost {
   CrtTabs crt{};
   std::vector<void*> allocs;
   ~EncHost() {
-    for (void* p : allocs) hipFree(p);
+    for (void* p : allocs) (void)hipFree(p);
   }
 };
 
@@ -99,6 +99,14 @@ EncodeArgs geometry_of(const pvfl_plan* p, const double* X, int64_t ld) {
     case PVFL_PLAN_CTMAT: a.bm = I.m_pad; a.bn = I.n_pad; a.width = std::max(I.m_pad, I.n_pad); break;
     case PVFL_PLAN_ROW: a.bm = I.m_pad; a.bn = I.n_pad; break;
   }
+  auto lg = [](int x) {
+    int r = 0;
+    while ((1 << r) < x) ++r;
+    return r;
+  };
+  a.lbn = lg(a.bn);
+  a.lmp = lg(a.mprime);
+  a.lw = lg(std::max(1, a.width));
   return a;
 }
 

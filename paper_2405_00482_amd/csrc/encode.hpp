@@ -24,6 +24,7 @@ struct EncodeArgs {
   int m, n, ld;    // operand shape; ld = row stride of X (elements)
   const double* X; // plaintext matrix (pt encode) or encrypted operand (ct encode)
   int bm, bn, mprime, col_blocks, width, pack, n_out, n_out_cts, slots;
+  int lbn, lmp, lw;  // log2 of bn, mprime, width (all powers of two)
   double scale;    // encoding scale
   double ind_scale;  // ROW: scale of the indicator plaintext
   int bsgs;          // HYBRID: baby-step size; diagonal i is stored rotated right by (i / bsgs) * bsgs

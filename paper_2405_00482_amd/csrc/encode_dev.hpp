@@ -23,40 +23,41 @@ __device__ __forceinline__ double round_half_away(double x) {
   return r;
 }
 
-// S radix-2 DIF stages s0 .. s0+S-1 of the M = N/2 point FFT, on register
+// S radix-2 DIF stages S0 .. S0+S-1 of the M = N/2 point FFT, on register
 // sets of 2^S elements {base + u * stride} (stride = half-length of the last
 // stage).  Each thread owns 8 elements (M = 8 T), i.e. 8 / 2^S sets; the sets
 // partition the array, so a set is loaded, transformed and written back in
 // place without a barrier in between.  At stage s a butterfly pairs elements
 // half_s = M >> (s+1) apart with twiddle W_M^(j 2^s), j = index mod half_s,
 // which for element u of a set is off + (u mod 2^(S-1-st)) * stride.
-template <int LOGN, int S>
-__device__ __forceinline__ void fft_pass(double2* a, int s0, const double2* __restrict__ tw, bool conj) {
+template <int LOGN, int S, int S0>
+__device__ __forceinline__ void fft_pass(double2* a, const double2* __restrict__ tw, bool conj) {
   constexpr int LOGM = LOGN - 1, M = 1 << LOGM, T = NttShape<LOGN>::T;
   constexpr int SET = 1 << S, NS = 8 >> S;
   static_assert(M == 8 * T, "eight FFT points per thread");
-  const int stride = M >> (s0 + S);
-  const int tid = threadIdx.x;
+  constexpr int LS = LOGM - S0 - S;  // log2 stride
+  constexpr unsigned stride = 1u << LS;
+  const unsigned tid = threadIdx.x;
   int base[NS], off[NS];
   double2 x[8];
 #pragma unroll
   for (int q = 0; q < NS; ++q) {
-    const int c = q * T + tid;
-    off[q] = c % stride;
-    base[q] = (c / stride) * (stride << S) + off[q];
+    const unsigned c = (unsigned)(q * T) + tid;
+    off[q] = (int)(c & (stride - 1u));
+    base[q] = (int)(((c >> LS) << (LS + S)) | (unsigned)off[q]);
 #pragma unroll
-    for (int u = 0; u < SET; ++u) x[q * SET + u] = a[cpad(base[q] + u * stride)];
+    for (int u = 0; u < SET; ++u) x[q * SET + u] = a[cpad(base[q] + (u << LS))];
   }
 #pragma unroll
   for (int st = 0; st < S; ++st) {
-    const int s = s0 + st;
+    const int s = S0 + st;
     const int hs = SET >> (st + 1);
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
 #pragma unroll
       for (int u = 0; u < SET; ++u) {
         if (u & hs) continue;
-        double2 w = tw[(off[q] + (u & (hs - 1)) * stride) << s];
+        double2 w = tw[(off[q] + ((u & (hs - 1)) << LS)) << s];
         if (conj) w = cconj(w);
         const double2 U = x[q * SET + u], V = x[q * SET + u + hs];
         x[q * SET + u] = make_double2(U.x + V.x, U.y + V.y);
@@ -67,8 +68,19 @@ __device__ __forceinline__ void fft_pass(double2* a, int s0, const double2* __re
 #pragma unroll
   for (int q = 0; q < NS; ++q)
 #pragma unroll
-    for (int u = 0; u < SET; ++u) a[cpad(base[q] + u * stride)] = x[q * SET + u];
+    for (int u = 0; u < SET; ++u) a[cpad(base[q] + (u << LS))] = x[q * SET + u];
   __syncthreads();
+}
+
+template <int LOGN, int S0>
+__device__ __forceinline__ void fft_passes(double2* a, const double2* __restrict__ tw, bool conj) {
+  constexpr int LEFT = LOGN - 1 - S0;
+  if constexpr (LEFT >= 3) {
+    fft_pass<LOGN, 3, S0>(a, tw, conj);
+    fft_passes<LOGN, S0 + 3>(a, tw, conj);
+  } else if constexpr (LEFT > 0) {
+    fft_pass<LOGN, LEFT, S0>(a, tw, conj);
+  }
 }
 
 // In-place DIF FFT over M = N/2 points in LDS (padded by cpad), sign -1
@@ -77,12 +89,7 @@ __device__ __forceinline__ void fft_pass(double2* a, int s0, const double2* __re
 // barrier.  Radix-8 register passes: ceil(log2(M) / 3) LDS round trips.
 template <int LOGN>
 __device__ __forceinline__ void fft_dif_lds(double2* a, const double2* __restrict__ tw, bool conj) {
-  constexpr int LOGM = LOGN - 1;
-  int s0 = 0;
-#pragma unroll 1
-  for (; s0 + 3 <= LOGM; s0 += 3) fft_pass<LOGN, 3>(a, s0, tw, conj);
-  if (LOGM - s0 == 2) fft_pass<LOGN, 2>(a, s0, tw, conj);
-  if (LOGM - s0 == 1) fft_pass<LOGN, 1>(a, s0, tw, conj);
+  fft_passes<LOGN, 0>(a, tw, conj);
 }
 
 __device__ __forceinline__ int brev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
@@ -91,18 +98,19 @@ __device__ __forceinline__ int brev(int x, int bits) { return (int)(__brev((unsi
 __device__ __forceinline__ double pt_slot_value(const EncodeArgs& a, int k, int s) {
   switch (a.kind) {
     case 0: {  // HYBRID: block (b, c), diagonal i; slot s = g bn + j
+      // bn, bm and m' are powers of two (zero padding, Sec. 3): shifts and masks
       const int per = a.col_blocks * a.mprime;
-      const int b = k / per, c = (k / a.mprime) % a.col_blocks, i = k % a.mprime;
-      if (a.bsgs > 0) s = (s - (i / a.bsgs) * a.bsgs + a.slots) & (a.slots - 1);  // pre-rotation by the giant step
-      const int g = s / a.bn, j = s % a.bn;
-      const int rr = g * a.mprime + (j % a.mprime);
+      const int b = k / per, c = (k >> a.lmp) % a.col_blocks, i = k & (a.mprime - 1);
+      if (a.bsgs > 0) s = (s - (i & -a.bsgs) + a.slots) & (a.slots - 1);  // pre-rotation by the giant step
+      const int g = s >> a.lbn, j = s & (a.bn - 1);
+      const int rr = (g << a.lmp) + (j & (a.mprime - 1));
       if (rr >= a.bm) return 0.0;
-      const int row = b * a.bm + rr, col = c * a.bn + (i + j) % a.bn;
+      const int row = b * a.bm + rr, col = c * a.bn + ((i + j) & (a.bn - 1));
       return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
     }
     case 1: {  // DIAG: Eq. 5 over max(m,n) slots
       if (s >= a.width) return 0.0;
-      const int row = s % a.bm, col = (k + s) % a.bn;
+      const int row = s & (a.bm - 1), col = (k + s) & (a.bn - 1);
       return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
     }
     case 2: {  // ROW: row k in slots 0..n-1
@@ -110,9 +118,9 @@ __device__ __forceinline__ double pt_slot_value(const EncodeArgs& a, int k, int 
     }
     case 3: {  // CTMAT: W (n x n_out); plaintext k = i * n_out_cts + kc
       const int i = k / a.n_out_cts, kc = k % a.n_out_cts;
-      const int blk = s / a.width, j = s % a.width;
+      const int blk = s >> a.lw, j = s & (a.width - 1);
       if (blk >= a.pack) return 0.0;
-      const int r = (i + j) % a.bn, col = kc * a.pack + blk;
+      const int r = (i + j) & (a.bn - 1), col = kc * a.pack + blk;
       return (r < a.n && col < a.n_out) ? a.X[(size_t)r * a.ld + col] : 0.0;
     }
   }
@@ -123,18 +131,18 @@ __device__ __forceinline__ double pt_slot_value(const EncodeArgs& a, int k, int 
 __device__ __forceinline__ double ct_slot_value(const EncodeArgs& a, int c, int t) {
   switch (a.kind) {
     case 0: {  // HYBRID: column block c of y, period bn
-      const int col = c * a.bn + (t % a.bn);
+      const int col = c * a.bn + (t & (a.bn - 1));
       return col < a.n ? a.X[col] : 0.0;
     }
     case 1:
     case 2: {  // DIAG / ROW: y with period n_pad
-      const int col = t % a.bn;
+      const int col = t & (a.bn - 1);
       return col < a.n ? a.X[col] : 0.0;
     }
     case 3: {  // CTMAT: diagonal c of A (m x n), replicated over pack blocks
-      const int blk = t / a.width, j = t % a.width;
+      const int blk = t >> a.lw, j = t & (a.width - 1);
       if (blk >= a.pack) return 0.0;
-      const int row = j % a.bm, col = (c + j) % a.bn;
+      const int row = j & (a.bm - 1), col = (c + j) & (a.bn - 1);
       return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
     }
   }
@@ -190,13 +198,14 @@ __device__ __forceinline__ void encode_pt_body(const EncodeArgs& a, int k, const
   } else {
     encode_to_regs<LOGN, false>(a, k, s2, mreg, et, a.scale);
   }
-  // coefficient tid + w T: w < 8 -> m_k (real part), w >= 8 -> m_(k+N/2) (imaginary part)
+  // coefficient tid + w T: w < 8 -> m_k (real part), w >= 8 -> m_(k+N/2) (imaginary part);
+  // |m| < 2^51, which the transform reduces on entry
   for (int l = 0; l < map.n; ++l) {
     const int pi = map.idx[l];
     const ModQ m = tb.mods[pi];
     double c[16];
 #pragma unroll
-    for (int w = 0; w < 16; ++w) c[w] = reduce(w < 8 ? mreg[2 * w] : mreg[2 * (w - 8) + 1], m);
+    for (int w = 0; w < 16; ++w) c[w] = w < 8 ? mreg[2 * w] : mreg[2 * (w - 8) + 1];
     ntt_fwd_regs<LOGN>(s, c, tb.fwd_tw + (size_t)pi * N, m);
     double* dst = out_pt + (size_t)l * N;
     for (int t = threadIdx.x; t < N; t += T) dst[t] = s[lds_pad(tb.perm[t])];

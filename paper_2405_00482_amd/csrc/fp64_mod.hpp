@@ -1,4 +1,4 @@
-// Exact modular arithmetic on binary64 for primes q < 2^49 (gfx950 VALU).
+// Exact modular arithmetic on binary64 for primes q < 2^48 (gfx950 VALU).
 //
 // Residues are integers held exactly in IEEE-754 binary64 (|x| < 2^53).  On
 // CDNA4 the FP64 FMA and round-to-integer instructions issue at full rate,
@@ -10,9 +10,10 @@
 //   r = fma(-k, q, h) + l                         =>  r = a*b - k*q exactly
 //
 // fma(-k, q, h) is exact because its result is an integer of magnitude below
-// 2^53, and r + l is exact for the same reason.  With |a| <= 4q, |b| <= q/2+1
-// and q < 2^49 the estimate k is within 0.88 of a*b/q, so |r| < q.  Every
-// function states the input range it needs and the output range it gives.
+// 2^53, and r + l is exact for the same reason.  The quotient estimate has
+// relative error below 3 * 2^-53, so with |a*b/q| < 2^50 (e.g. |a| <= 2^51,
+// |b| <= q/2 + 1) k is within 0.875 of a*b/q and |r| < q.  Every function
+// states the input range it needs and the output range it gives.
 // Compile with -ffp-contract=off: contraction would change h and break the
 // identity a*b = h + l.
 #pragma once

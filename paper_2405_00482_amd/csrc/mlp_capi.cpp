@@ -24,7 +24,7 @@ struct pvfl_mlp {
   float *params = nullptr, *m = nullptr, *v = nullptr, *g = nullptr, *gs = nullptr, *lb = nullptr, *loss = nullptr;
   ~pvfl_mlp() {
     for (float* p : {params, m, v, g, gs, lb, loss})
-      if (p) hipFree(p);
+      if (p) (void)hipFree(p);
   }
 };
 

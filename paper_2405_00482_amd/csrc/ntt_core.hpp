@@ -16,9 +16,11 @@
 // padded by one double every 16 (lds_pad) so that the strided set loads of
 // every pass are close to bank-conflict free.
 //
-// Value ranges: inputs may be any integers with |x| < 2^51; values are
-// re-centred at the end of every pass (forward) or every second stage
-// (inverse), so every mulmod sees |a| <= 4q; outputs are centred.
+// Value ranges (q < 2^48): inputs may be any integers with |x| < 2^51.  A
+// twiddle mulmod of |a| <= 2^51 returns |r| < q, so a forward butterfly grows
+// values by less than q; re-centring at least every 7 stages keeps them below
+// q/2 + 7q < 2^51.  The inverse re-centres its sums every second stage.
+// Outputs are centred.
 #pragma once
 #include "fp64_mod.hpp"
 
@@ -44,14 +46,46 @@ struct NttShape {
 
 __device__ __forceinline__ int lds_pad(int j) { return j + (j >> 4); }
 
-// S radix-2 Cooley-Tukey stages lg0 .. lg0+S-1 on register sets.  Each thread
-// owns 16 / 2^S sets of 2^S elements {base + u * stride}, stride = span of the
-// last stage of the pass.  A set lies inside one butterfly group of stage lg0
-// (group g0 = base >> (LOGN - lg0)); at stage lg0 + st it spans 2^st groups
-// g0 * 2^st + k, whose twiddles are contiguous in the table, so a pass reads
-// 2^S - 1 twiddles per set.
+// Pass geometry.  A pass of S radix-2 stages works on register sets of 2^S
+// elements {base + u * 2^ls} (2^ls = span of the pass's last stage); thread
+// tid owns sets c = q*T + tid, q < 16 / 2^S, with base = blk * 2^(ls+S) + off,
+// blk = c >> ls, off = c mod 2^ls.  Strides are powers of two, so the index
+// arithmetic is shifts and masks.  (The pass loops stay rolled: unrolling
+// them lets the scheduler overlap passes and the register file overflows.)
 template <int LOGN, int S>
-__device__ __forceinline__ void ct_pass_regs(double (&x)[16], int lg0, const int (&base)[16 >> S], int /*stride*/,
+__device__ __forceinline__ void pass_bases(int (&base)[16 >> S], int ls) {
+  constexpr int T = NttShape<LOGN>::T;
+#pragma unroll
+  for (int q = 0; q < (16 >> S); ++q) {
+    const unsigned c = (unsigned)(q * T) + threadIdx.x;
+    base[q] = (int)(((c >> ls) << (ls + S)) | (c & ((1u << ls) - 1u)));
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void lds_load_sets(const double* s, double (&x)[16], const int (&base)[16 >> S], int ls) {
+#pragma unroll
+  for (int q = 0; q < (16 >> S); ++q)
+#pragma unroll
+    for (int u = 0; u < (1 << S); ++u) x[q * (1 << S) + u] = s[lds_pad(base[q] + (u << ls))];
+}
+template <int S>
+__device__ __forceinline__ void lds_store_sets(double* s, const double (&x)[16], const int (&base)[16 >> S], int ls) {
+#pragma unroll
+  for (int q = 0; q < (16 >> S); ++q)
+#pragma unroll
+    for (int u = 0; u < (1 << S); ++u) s[lds_pad(base[q] + (u << ls))] = x[q * (1 << S) + u];
+}
+
+// S radix-2 Cooley-Tukey stages lg0 .. lg0+S-1 on the register sets.  A set
+// lies inside one butterfly group of stage lg0 (group g0 = base >> (LOGN -
+// lg0)); at stage lg0 + st it spans 2^st groups g0 * 2^st + k, whose
+// twiddles are contiguous in the table, so a pass reads 2^S - 1 twiddles per
+// set.  No reduction here: a butterfly adds less than q in magnitude (the
+// mulmod output is below q), and the caller re-centres often enough that
+// every value stays below 2^51.
+template <int LOGN, int S>
+__device__ __forceinline__ void ct_pass_regs(double (&x)[16], int lg0, const int (&base)[16 >> S],
                                              const double* __restrict__ tw, ModQ m) {
   constexpr int SET = 1 << S;
 #pragma unroll
@@ -74,71 +108,49 @@ __device__ __forceinline__ void ct_pass_regs(double (&x)[16], int lg0, const int
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < 16; ++k) x[k] = reduce(x[k], m);
 }
 
-// set bases of a pass: set c = q*T + tid, blocks of SET*stride elements
-template <int LOGN, int S>
-__device__ __forceinline__ void pass_bases(int (&base)[16 >> S], int stride) {
-  constexpr int T = NttShape<LOGN>::T;
+template <int N>
+__device__ __forceinline__ void recentre(double (&x)[N], ModQ m) {
 #pragma unroll
-  for (int q = 0; q < (16 >> S); ++q) {
-    const int c = q * T + (int)threadIdx.x;
-    const int blk = c / stride, off = c % stride;
-    base[q] = blk * (stride << S) + off;
-  }
-}
-
-template <int LOGN, int S>
-__device__ __forceinline__ void lds_load_sets(const double* s, double (&x)[16], const int (&base)[16 >> S], int stride) {
-#pragma unroll
-  for (int q = 0; q < (16 >> S); ++q)
-#pragma unroll
-    for (int u = 0; u < (1 << S); ++u) x[q * (1 << S) + u] = s[lds_pad(base[q] + u * stride)];
-}
-template <int LOGN, int S>
-__device__ __forceinline__ void lds_store_sets(double* s, const double (&x)[16], const int (&base)[16 >> S], int stride) {
-#pragma unroll
-  for (int q = 0; q < (16 >> S); ++q)
-#pragma unroll
-    for (int u = 0; u < (1 << S); ++u) s[lds_pad(base[q] + u * stride)] = x[q * (1 << S) + u];
+  for (int k = 0; k < N; ++k) x[k] = reduce(x[k], m);
 }
 
 // Forward transform.  c[w] is coefficient tid + w*T of the thread (natural
 // order, any |x| < 2^51); the first pass runs on these registers directly.
-// The result is left in LDS in bit-reversed order: read it with
+// The result is left in LDS in bit-reversed order, centred: read it with
 // s[lds_pad(perm[t])] after the call (which ends with a barrier).  The call
 // begins with a barrier, so `s` may still be in use by the caller before it.
+// Re-centring: after every 4-stage pass; the short first pass (S0 < 4 stages)
+// is followed by a 4-stage pass before the first re-centring (S0 + 4 <= 7).
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd_regs(double* s, const double (&c)[16], const double* __restrict__ tw, ModQ m) {
   constexpr int S0 = NttShape<LOGN>::S0;
+  constexpr int S = S0 > 0 ? S0 : 4;
   double x[16];
-  int lg = 0;
   {
-    constexpr int S = S0 > 0 ? S0 : 4;
-    const int stride = 1 << (LOGN - S);
     int base[16 >> S];
-    pass_bases<LOGN, S>(base, stride);
-    // register slot (q, u) holds coefficient base[q] + u*stride = tid + T*(q + u*(16>>S))
+    pass_bases<LOGN, S>(base, LOGN - S);
+    // register slot (q, u) holds coefficient base[q] + u*2^(LOGN-S) = tid + T*(q + u*(16>>S))
 #pragma unroll
     for (int q = 0; q < (16 >> S); ++q)
 #pragma unroll
       for (int u = 0; u < (1 << S); ++u) x[q * (1 << S) + u] = reduce(c[q + u * (16 >> S)], m);
-    ct_pass_regs<LOGN, S>(x, 0, base, stride, tw, m);
+    ct_pass_regs<LOGN, S>(x, 0, base, tw, m);
+    if (S == 4) recentre(x, m);
     __syncthreads();
-    lds_store_sets<LOGN, S>(s, x, base, stride);
-    lg = S;
+    lds_store_sets<S>(s, x, base, LOGN - S);
   }
   __syncthreads();
 #pragma unroll 1
-  for (; lg < LOGN; lg += 4) {
-    const int stride = 1 << (LOGN - lg - 4);
+  for (int lg = S; lg < LOGN; lg += 4) {
+    const int ls = LOGN - lg - 4;
     int base[1];
-    pass_bases<LOGN, 4>(base, stride);
-    lds_load_sets<LOGN, 4>(s, x, base, stride);
-    ct_pass_regs<LOGN, 4>(x, lg, base, stride, tw, m);
-    lds_store_sets<LOGN, 4>(s, x, base, stride);
+    pass_bases<LOGN, 4>(base, ls);
+    lds_load_sets<4>(s, x, base, ls);
+    ct_pass_regs<LOGN, 4>(x, lg, base, tw, m);
+    recentre(x, m);
+    lds_store_sets<4>(s, x, base, ls);
     __syncthreads();
   }
 }
@@ -153,12 +165,13 @@ __device__ __forceinline__ void ntt_fwd(double* s, Load load, const double* __re
   ntt_fwd_regs<LOGN>(s, c, tw, m);
 }
 
-// S Gentleman-Sande stages, lg1, lg1-1, ..., lg1-S+1 (span doubling each
-// stage); sets {base + u * stride}, stride = span of the first stage.  The
-// set is one group of stage lg1-S+1; at stage lg1-st it spans 2^(S-1-st)
-// groups with contiguous twiddles.
+// S Gentleman-Sande stages lg1, lg1-1, ..., lg1-S+1 (span doubling each
+// stage); sets {base + u * 2^ls}, 2^ls = span of the first stage.  The set is
+// one group of stage lg1-S+1; at stage lg1-st it spans 2^(S-1-st) groups with
+// contiguous twiddles.  Sums are re-centred every second stage, differences
+// go through mulmod; everything is re-centred at the end.
 template <int LOGN, int S>
-__device__ __forceinline__ void gs_pass_regs(double (&x)[16], int lg1, const int (&base)[16 >> S], int /*stride*/,
+__device__ __forceinline__ void gs_pass_regs(double (&x)[16], int lg1, const int (&base)[16 >> S],
                                              const double* __restrict__ itw, ModQ m) {
   constexpr int SET = 1 << S;
 #pragma unroll
@@ -184,8 +197,7 @@ __device__ __forceinline__ void gs_pass_regs(double (&x)[16], int lg1, const int
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < 16; ++k) x[k] = reduce(x[k], m);
+  recentre(x, m);
 }
 
 // Inverse transform of the bit-reversed data already in LDS (padded, after a
@@ -201,21 +213,21 @@ __device__ __forceinline__ void ntt_inv_regs(double* s, double (&c)[16], const d
   constexpr int NFULL = S0 > 0 ? 3 : 2;
 #pragma unroll 1
   for (int p = 0; p < NFULL; ++p, lg1 -= 4) {
-    const int stride = 1 << (LOGN - 1 - lg1);
+    const int ls = LOGN - 1 - lg1;
     int base[1];
-    pass_bases<LOGN, 4>(base, stride);
-    lds_load_sets<LOGN, 4>(s, x, base, stride);
-    gs_pass_regs<LOGN, 4>(x, lg1, base, stride, itw, m);
-    lds_store_sets<LOGN, 4>(s, x, base, stride);
+    pass_bases<LOGN, 4>(base, ls);
+    lds_load_sets<4>(s, x, base, ls);
+    gs_pass_regs<LOGN, 4>(x, lg1, base, itw, m);
+    lds_store_sets<4>(s, x, base, ls);
     __syncthreads();
   }
   {
     constexpr int S = S0 > 0 ? S0 : 4;
-    const int stride = 1 << (LOGN - 1 - lg1);
+    const int ls = LOGN - 1 - lg1;
     int base[16 >> S];
-    pass_bases<LOGN, S>(base, stride);
-    lds_load_sets<LOGN, S>(s, x, base, stride);
-    gs_pass_regs<LOGN, S>(x, lg1, base, stride, itw, m);
+    pass_bases<LOGN, S>(base, ls);
+    lds_load_sets<S>(s, x, base, ls);
+    gs_pass_regs<LOGN, S>(x, lg1, base, itw, m);
 #pragma unroll
     for (int q = 0; q < (16 >> S); ++q)
 #pragma unroll

@@ -44,9 +44,9 @@ static int ilog2(int x) {
 }
 
 pvfl_plan::~pvfl_plan() {
-  if (iota_dev) hipFree(iota_dev);
-  if (rot_dev) hipFree(rot_dev);
-  if (own_ws) hipFree(own_ws);
+  if (iota_dev) (void)hipFree(iota_dev);
+  if (rot_dev) (void)hipFree(rot_dev);
+  if (own_ws) (void)hipFree(own_ws);
 }
 
 static uint32_t galois_rotl(int i, int N) {
@@ -277,7 +277,7 @@ static pvfl_status get_ws(const pvfl_plan* p, void* ws, size_t ws_bytes, double*
     return PVFL_OK;
   }
   if (p->own_ws_bytes < need) {
-    if (p->own_ws) hipFree(p->own_ws);
+    if (p->own_ws) (void)hipFree(p->own_ws);
     p->own_ws = nullptr;
     p->own_ws_bytes = 0;
     if (hipMalloc((void**)&p->own_ws, need) != hipSuccess) return fail(PVFL_E_NOMEM, "workspace allocation");

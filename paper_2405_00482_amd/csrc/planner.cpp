@@ -126,8 +126,8 @@ struct pvfl_planner {
   float* x_dev = nullptr;   // [kMaxCandidates][kFeatures]
   float* y_dev = nullptr;   // [kMaxCandidates]
   ~pvfl_planner() {
-    if (x_dev) hipFree(x_dev);
-    if (y_dev) hipFree(y_dev);
+    if (x_dev) (void)hipFree(x_dev);
+    if (y_dev) (void)hipFree(y_dev);
   }
 };
 
