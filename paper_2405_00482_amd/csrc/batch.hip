@@ -247,6 +247,7 @@ __global__ __launch_bounds__(256) void k_readout_batch(const double* __restrict_
     case 12: FN<12>(__VA_ARGS__); break;                  \
     case 13: FN<13>(__VA_ARGS__); break;                  \
     case 14: FN<14>(__VA_ARGS__); break;                  \
+    case 15: FN<15>(__VA_ARGS__); break;                  \
     default: return hipErrorInvalidValue;                 \
   }
 

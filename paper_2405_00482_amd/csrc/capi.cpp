@@ -206,7 +206,7 @@ static void build_ks_level(const pvfl_ctx* c, int lv, KsLevel& kl) {
 extern "C" pvfl_status pvfl_context_create(const pvfl_params* prm, int device, pvfl_ctx** out) {
   if (!prm || !out) return fail(PVFL_E_INVALID, "null argument");
   *out = nullptr;
-  if (prm->log_n < 12 || prm->log_n > 14) return fail(PVFL_E_INVALID, "log_n must be 12..14");
+  if (prm->log_n < 12 || prm->log_n > 15) return fail(PVFL_E_INVALID, "log_n must be 12..15");
   if (prm->n_q < 1 || prm->n_p < 1 || prm->n_p > (uint32_t)kMaxAlpha || prm->n_q + prm->n_p > (uint32_t)kMaxLimbs)
     return fail(PVFL_E_INVALID, "unsupported prime counts");
   const int N = 1 << prm->log_n;
@@ -242,6 +242,27 @@ extern "C" pvfl_status pvfl_context_create(const pvfl_params* prm, int device, p
     }
     ninv[pi] = centred(invm((u64)N % q, q), q);
     two32[pi] = centred((1ull << 32) % q, q);
+    if (c->logN == 15) {
+      // split layout: half h's 2^14-point table at h * N/2 (entry (1 << lg) + g is
+      // the full table's (1 << (lg + 1)) + (h << lg) + g), the first stage's
+      // twiddle at index 0
+      const int H = N / 2;
+      std::vector<double> f(N, 0.0), iv(N, 0.0);
+      double* fr = &fwd[(size_t)pi * N];
+      double* ir = &inv[(size_t)pi * N];
+      f[0] = fr[1];
+      iv[0] = ir[1];
+      for (int h = 0; h < 2; ++h)
+        for (int k = 1; k < H; ++k) {
+          int lg = 0;
+          while ((2 << lg) <= k) ++lg;
+          const int src = (1 << (lg + 1)) + (h << lg) + (k - (1 << lg));
+          f[(size_t)h * H + k] = fr[src];
+          iv[(size_t)h * H + k] = ir[src];
+        }
+      std::copy(f.begin(), f.end(), fr);
+      std::copy(iv.begin(), iv.end(), ir);
+    }
   }
   // orbit order t -> bit-reversed index
   std::vector<uint32_t> perm(N);

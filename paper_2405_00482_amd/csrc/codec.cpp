@@ -62,13 +62,16 @@ pvfl_status enc_tables(pvfl_ctx* c, EncHost** out) {
   std::vector<double> ginv(kMaxLimbs * kMaxLimbs, 0.0);
   for (int i = 0; i < c->n_q; ++i)
     for (int j = 0; j < i; ++j) ginv[j * kMaxLimbs + i] = centred(invm(c->primes[j] % c->primes[i], c->primes[i]), c->primes[i]);
-  void *d_s2f, *d_tw, *d_twist, *d_g;
+  std::vector<uint32_t> f2slot(M);
+  for (int j = 0; j < M; ++j) f2slot[slot2f[j]] = (uint32_t)j;
+  void *d_s2f, *d_f2s, *d_tw, *d_twist, *d_g;
   pvfl_status st;
   if ((st = upload(h.get(), slot2f.data(), sizeof(uint32_t) * M, &d_s2f)) != PVFL_OK) return st;
+  if ((st = upload(h.get(), f2slot.data(), sizeof(uint32_t) * M, &d_f2s)) != PVFL_OK) return st;
   if ((st = upload(h.get(), tw.data(), sizeof(double2) * (M / 2), &d_tw)) != PVFL_OK) return st;
   if ((st = upload(h.get(), twist.data(), sizeof(double2) * M, &d_twist)) != PVFL_OK) return st;
   if ((st = upload(h.get(), ginv.data(), sizeof(double) * ginv.size(), &d_g)) != PVFL_OK) return st;
-  h->et = EncTabs{(const uint32_t*)d_s2f, (const double2*)d_tw, (const double2*)d_twist};
+  h->et = EncTabs{(const uint32_t*)d_s2f, (const uint32_t*)d_f2s, (const double2*)d_tw, (const double2*)d_twist};
   h->crt = CrtTabs{c->tabs.mods, (const double*)d_g};
   c->enc_tabs = h.release();
   c->enc_tabs_free = [](void* p) { delete (EncHost*)p; };

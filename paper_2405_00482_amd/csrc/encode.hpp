@@ -9,6 +9,7 @@ namespace pvfl {
 
 struct EncTabs {
   const uint32_t* slot2f;   // [N/2] slot j -> DFT index f_j = (5^j mod 2N - 1) / 4
+  const uint32_t* f2slot;   // [N/2] the inverse permutation
   const double2* fft_tw;    // [N/4] exp(-2 pi i t / (N/2))
   const double2* twist;     // [N/2] zeta^k = exp(i pi k / N)
 };

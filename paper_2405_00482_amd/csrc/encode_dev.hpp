@@ -30,7 +30,7 @@ __device__ __forceinline__ double round_half_away(double x) {
 // place without a barrier in between.  At stage s a butterfly pairs elements
 // half_s = M >> (s+1) apart with twiddle W_M^(j 2^s), j = index mod half_s,
 // which for element u of a set is off + (u mod 2^(S-1-st)) * stride.
-template <int LOGN, int S, int S0>
+template <int LOGN, int S, int S0, int TWSH>
 __device__ __forceinline__ void fft_pass(double2* a, const double2* __restrict__ tw, bool conj) {
   constexpr int LOGM = LOGN - 1, M = 1 << LOGM, T = NttShape<LOGN>::T;
   constexpr int SET = 1 << S, NS = 8 >> S;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void fft_pass(double2* a, const double2* __restrict__
 #pragma unroll
       for (int u = 0; u < SET; ++u) {
         if (u & hs) continue;
-        double2 w = tw[(off[q] + ((u & (hs - 1)) << LS)) << s];
+        double2 w = tw[((off[q] + ((u & (hs - 1)) << LS)) << s) << TWSH];
         if (conj) w = cconj(w);
         const double2 U = x[q * SET + u], V = x[q * SET + u + hs];
         x[q * SET + u] = make_double2(U.x + V.x, U.y + V.y);
@@ -72,14 +72,16 @@ __device__ __forceinline__ void fft_pass(double2* a, const double2* __restrict__
   __syncthreads();
 }
 
-template <int LOGN, int S0>
+// TWSH = 1 runs the 2^(LOGN-1)-point transform with the table of twice that
+// size (every second entry), as the halves of the 2^15 ring's FFT do
+template <int LOGN, int S0, int TWSH = 0>
 __device__ __forceinline__ void fft_passes(double2* a, const double2* __restrict__ tw, bool conj) {
   constexpr int LEFT = LOGN - 1 - S0;
   if constexpr (LEFT >= 3) {
-    fft_pass<LOGN, 3, S0>(a, tw, conj);
-    fft_passes<LOGN, S0 + 3>(a, tw, conj);
+    fft_pass<LOGN, 3, S0, TWSH>(a, tw, conj);
+    fft_passes<LOGN, S0 + 3, TWSH>(a, tw, conj);
   } else if constexpr (LEFT > 0) {
-    fft_pass<LOGN, LEFT, S0>(a, tw, conj);
+    fft_pass<LOGN, LEFT, S0, TWSH>(a, tw, conj);
   }
 }
 
@@ -89,7 +91,15 @@ __device__ __forceinline__ void fft_passes(double2* a, const double2* __restrict
 // barrier.  Radix-8 register passes: ceil(log2(M) / 3) LDS round trips.
 template <int LOGN>
 __device__ __forceinline__ void fft_dif_lds(double2* a, const double2* __restrict__ tw, bool conj) {
+  static_assert(LOGN <= 14, "the 2^15 ring's FFT is split in halves (encode_to_regs, k_decode)");
   fft_passes<LOGN, 0>(a, tw, conj);
+}
+
+// Half h of the 2^15 ring's M = 2^14 point DIF FFT, already past its first
+// stage and placed in LDS: stages 1.. of the full transform restricted to
+// the half are a 2^13-point DIF FFT with twiddle indices doubled.
+__device__ __forceinline__ void fft_dif_half15(double2* a, const double2* __restrict__ tw, bool conj) {
+  fft_passes<14, 0, 1>(a, tw, conj);
 }
 
 __device__ __forceinline__ int brev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
@@ -149,28 +159,65 @@ __device__ __forceinline__ double ct_slot_value(const EncodeArgs& a, int c, int 
   return 0.0;
 }
 
-// slots -> LDS FFT -> rounded coefficients in registers (mreg[2u] = m_k,
-// mreg[2u+1] = m_(k+N/2), k = tid + u T)
+// slots -> FFT -> rounded coefficients in registers: mreg[2u] = m_k and
+// mreg[2u+1] = m_(k+N/2) for k = tid + u T, u < M/T.  val(s) is the scaled
+// value of slot s.  At N = 2^15 the first DIF stage (pairs i, i + M/2, owned
+// by one thread) runs in registers and the two halves in LDS one after the
+// other; half h yields the coefficients with k = h mod 2.
+template <int LOGN, class Val>
+__device__ __forceinline__ void encode_to_regs_v(Val val, double2* z, double* mreg, const EncTabs& et) {
+  constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T, PH = M / T;
+  const int tid = threadIdx.x;
+  const double inv_m = 1.0 / (double)M;
+  if constexpr (LOGN <= 14) {
+    for (int s = tid; s < M; s += T) z[cpad(et.slot2f[s])] = make_double2(val(s), 0.0);
+    __syncthreads();
+    fft_dif_lds<LOGN>(z, et.fft_tw, false);
+#pragma unroll
+    for (int u = 0; u < PH; ++u) {
+      const int kk = tid + u * T;
+      const double2 w = cmul(z[cpad(brev(kk, LOGN - 1))], cconj(et.twist[kk]));
+      mreg[2 * u] = round_half_away(w.x * inv_m);
+      mreg[2 * u + 1] = round_half_away(w.y * inv_m);
+    }
+  } else {
+    constexpr int HM = M / 2;
+    double2 v0[HM / T];
+#pragma unroll
+    for (int u = 0; u < HM / T; ++u) {
+      const int i = tid + u * T;
+      const double a0 = val(et.f2slot[i]), b0 = val(et.f2slot[i + HM]);
+      z[cpad(i)] = make_double2(a0 + b0, 0.0);
+      v0[u] = cmul(make_double2(a0 - b0, 0.0), et.fft_tw[i]);
+    }
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      if (h) {
+        __syncthreads();  // half 0's read-out is done
+#pragma unroll
+        for (int u = 0; u < HM / T; ++u) z[cpad(tid + u * T)] = v0[u];
+      }
+      __syncthreads();
+      fft_dif_half15(z, et.fft_tw, false);
+      if ((tid & 1) == h) {  // k = tid + u T has the parity of tid
+#pragma unroll
+        for (int u = 0; u < PH; ++u) {
+          const int kk = tid + u * T;
+          const double2 w = cmul(z[cpad(brev(kk, LOGN - 1) - h * HM)], cconj(et.twist[kk]));
+          mreg[2 * u] = round_half_away(w.x * inv_m);
+          mreg[2 * u + 1] = round_half_away(w.y * inv_m);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <int LOGN, bool CT>
 __device__ __forceinline__ void encode_to_regs(const EncodeArgs& a, int k, double2* z, double* mreg, const EncTabs& et,
                                                double scale) {
-  constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T, PH = M / T;
-  const int tid = threadIdx.x;
-  for (int s = tid; s < M; s += T) {
-    const double v = CT ? ct_slot_value(a, k, s) : pt_slot_value(a, k, s);
-    z[cpad(et.slot2f[s])] = make_double2(v * scale, 0.0);
-  }
-  __syncthreads();
-  fft_dif_lds<LOGN>(z, et.fft_tw, false);
-  const double inv_m = 1.0 / (double)M;
-#pragma unroll
-  for (int u = 0; u < PH; ++u) {
-    const int kk = tid + u * T;
-    const double2 w = cmul(z[cpad(brev(kk, LOGN - 1))], cconj(et.twist[kk]));
-    mreg[2 * u] = round_half_away(w.x * inv_m);
-    mreg[2 * u + 1] = round_half_away(w.y * inv_m);
-  }
-  __syncthreads();
+  encode_to_regs_v<LOGN>([&](int s) { return (CT ? ct_slot_value(a, k, s) : pt_slot_value(a, k, s)) * scale; }, z,
+                         mreg, et);
 }
 
 
@@ -179,36 +226,26 @@ __device__ __forceinline__ void encode_to_regs(const EncodeArgs& a, int k, doubl
 template <int LOGN>
 __device__ __forceinline__ void encode_pt_body(const EncodeArgs& a, int k, const EncTabs& et, const LimbMap& map,
                                                const DevTabs& tb, double2* s2, double* __restrict__ out_pt) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PH = N / 2 / T;
+  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PH = N / 2 / T, PER = NttShape<LOGN>::PER;
   double* s = (double*)s2;
   double mreg[2 * PH];
   if (a.kind == 2 && k == a.m) {
     // ROW indicator plaintext: 1 in slot 0 at scale q_(l-1)
-    for (int t = threadIdx.x; t < N / 2; t += T) s2[cpad(et.slot2f[t])] = make_double2(t == 0 ? a.ind_scale : 0.0, 0.0);
-    __syncthreads();
-    fft_dif_lds<LOGN>(s2, et.fft_tw, false);
-    const double inv_m = 1.0 / (double)(N / 2);
-#pragma unroll
-    for (int u = 0; u < PH; ++u) {
-      const int kk = threadIdx.x + u * T;
-      const double2 w = cmul(s2[cpad(brev(kk, LOGN - 1))], cconj(et.twist[kk]));
-      mreg[2 * u] = round_half_away(w.x * inv_m);
-      mreg[2 * u + 1] = round_half_away(w.y * inv_m);
-    }
+    const double ind = a.ind_scale;
+    encode_to_regs_v<LOGN>([&](int t) { return t == 0 ? ind : 0.0; }, s2, mreg, et);
   } else {
     encode_to_regs<LOGN, false>(a, k, s2, mreg, et, a.scale);
   }
-  // coefficient tid + w T: w < 8 -> m_k (real part), w >= 8 -> m_(k+N/2) (imaginary part);
+  // coefficient tid + w T: w < PH -> m_k (real part), w >= PH -> m_(k+N/2) (imaginary part);
   // |m| < 2^51, which the transform reduces on entry
   for (int l = 0; l < map.n; ++l) {
     const int pi = map.idx[l];
     const ModQ m = tb.mods[pi];
-    double c[16];
+    double c[PER];
 #pragma unroll
-    for (int w = 0; w < 16; ++w) c[w] = w < 8 ? mreg[2 * w] : mreg[2 * (w - 8) + 1];
-    ntt_fwd_regs<LOGN>(s, c, tb.fwd_tw + (size_t)pi * N, m);
+    for (int w = 0; w < PER; ++w) c[w] = w < PH ? mreg[2 * w] : mreg[2 * (w - PH) + 1];
     double* dst = out_pt + (size_t)l * N;
-    for (int t = threadIdx.x; t < N; t += T) dst[t] = s[lds_pad(tb.perm[t])];
+    ntt_fwd_regs_out<LOGN>(s, c, tb.fwd_tw + (size_t)pi * N, tb.perm, m, [&](int t, double v) { dst[t] = v; });
   }
 }
 

@@ -53,33 +53,59 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_decode(const double* __re
   const int c = blockIdx.x;
   const double* base = res + (size_t)c * (lv + 1) * N;
   const int nl = lv + 1;
-  for (int k = threadIdx.x; k < M; k += T) {
-    double val[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int kk = k + h * M;
-      double v[kMaxLimbs];
-      for (int i = 0; i < nl; ++i) {
-        const ModQ m = ct.mods[i];
-        double x = base[(size_t)i * N + kk];
-        for (int j = 0; j < i; ++j) x = mulmod(x - v[j], ct.garner_inv[j * kMaxLimbs + i], m);
-        v[i] = canon(x, m);
-      }
-      // sign: compare with the mixed-radix digits of (Q-1)/2 from the top
-      int cmp = 0;
-      for (int i = nl - 1; i >= 0 && cmp == 0; --i) {
-        const double h2 = 0.5 * (ct.mods[i].q - 1.0);
-        cmp = (v[i] > h2) ? 1 : ((v[i] < h2) ? -1 : 0);
-      }
-      double acc = (cmp > 0) ? v[nl - 1] - ct.mods[nl - 1].q : v[nl - 1];
-      for (int i = nl - 2; i >= 0; --i) acc = acc * ct.mods[i].q + v[i];
-      val[h] = acc;
+  // centred CRT lift of coefficient kk
+  auto lift = [&](int kk) {
+    double v[kMaxLimbs];
+    for (int i = 0; i < nl; ++i) {
+      const ModQ m = ct.mods[i];
+      double x = base[(size_t)i * N + kk];
+      for (int j = 0; j < i; ++j) x = mulmod(x - v[j], ct.garner_inv[j * kMaxLimbs + i], m);
+      v[i] = canon(x, m);
     }
-    w[cpad(k)] = cmul(make_double2(val[0], val[1]), et.twist[k]);
+    // sign: compare with the mixed-radix digits of (Q-1)/2 from the top
+    int cmp = 0;
+    for (int i = nl - 1; i >= 0 && cmp == 0; --i) {
+      const double h2 = 0.5 * (ct.mods[i].q - 1.0);
+      cmp = (v[i] > h2) ? 1 : ((v[i] < h2) ? -1 : 0);
+    }
+    double acc = (cmp > 0) ? v[nl - 1] - ct.mods[nl - 1].q : v[nl - 1];
+    for (int i = nl - 2; i >= 0; --i) acc = acc * ct.mods[i].q + v[i];
+    return acc;
+  };
+  // twisted w_k = (m_k + i m_(k+N/2)) zeta^k
+  auto twisted = [&](int k) { return cmul(make_double2(lift(k), lift(k + M)), et.twist[k]); };
+  double* zc = z + (size_t)c * M;
+  if constexpr (LOGN <= 14) {
+    for (int k = threadIdx.x; k < M; k += T) w[cpad(k)] = twisted(k);
+    __syncthreads();
+    fft_dif_lds<LOGN>(w, et.fft_tw, true);
+    for (int j = threadIdx.x; j < M; j += T) zc[j] = w[cpad(brev(et.slot2f[j], LOGN - 1))].x * inv_scale;
+  } else {
+    // first DIF stage (pairs k, k + M/2) in registers, then the two halves in LDS
+    constexpr int HM = M / 2;
+    double2 v0[HM / T];
+#pragma unroll
+    for (int u = 0; u < HM / T; ++u) {
+      const int k = threadIdx.x + u * T;
+      const double2 a0 = twisted(k), b0 = twisted(k + HM);
+      w[cpad(k)] = make_double2(a0.x + b0.x, a0.y + b0.y);
+      v0[u] = cmul(make_double2(a0.x - b0.x, a0.y - b0.y), cconj(et.fft_tw[k]));
+    }
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      if (h) {
+        __syncthreads();  // half 0's read-out is done
+#pragma unroll
+        for (int u = 0; u < HM / T; ++u) w[cpad(threadIdx.x + u * T)] = v0[u];
+      }
+      __syncthreads();
+      fft_dif_half15(w, et.fft_tw, true);
+      for (int j = threadIdx.x; j < M; j += T) {
+        const int r = brev(et.slot2f[j], LOGN - 1);
+        if ((r >> (LOGN - 2)) == h) zc[j] = w[cpad(r - h * HM)].x * inv_scale;
+      }
+    }
   }
-  __syncthreads();
-  fft_dif_lds<LOGN>(w, et.fft_tw, true);
-  for (int j = threadIdx.x; j < M; j += T) z[(size_t)c * M + j] = w[cpad(brev(et.slot2f[j], LOGN - 1))].x * inv_scale;
 }
 
 // lazy rotate-and-sum / read-out of the decoded slots (Sec. 4.3)
@@ -142,6 +168,7 @@ static void decode_impl(const LaunchCtx& L, const double* res, int nct, int lv, 
     case 12: FN<12>(__VA_ARGS__); break;                  \
     case 13: FN<13>(__VA_ARGS__); break;                  \
     case 14: FN<14>(__VA_ARGS__); break;                  \
+    case 15: FN<15>(__VA_ARGS__); break;                  \
     default: return hipErrorInvalidValue;                 \
   }
 

@@ -24,8 +24,9 @@ NTT_KERNEL(LOGN) void k_ntt_fwd(const double* __restrict__ in, double* __restric
   const int b = blockIdx.x, pi = map.idx[b % map.n];
   const ModQ m = tb.mods[pi];
   const double* src = in + (size_t)b * N;
-  ntt_fwd<LOGN>(s, [&](int j) { return src[j]; }, tb.fwd_tw + (size_t)pi * N, m);
-  store_orbit<LOGN>(s, out + (size_t)b * N, tb.perm);
+  double* dst = out + (size_t)b * N;
+  ntt_fwd_out<LOGN>(s, [&](int j) { return src[j]; }, tb.fwd_tw + (size_t)pi * N, tb.perm, m,
+                    [&](int t, double v) { dst[t] = v; });
 }
 
 template <int LOGN>
@@ -34,9 +35,10 @@ NTT_KERNEL(LOGN) void k_ntt_inv(const double* __restrict__ in, double* __restric
   NTT_LDS(LOGN);
   const int b = blockIdx.x, pi = map.idx[b % map.n];
   const ModQ m = tb.mods[pi];
-  lds_from_orbit<LOGN>(s, in + (size_t)b * N, tb.perm, m);
+  const double* src = in + (size_t)b * N;
   double* dst = out + (size_t)b * N;
-  ntt_inv<LOGN>(s, [&](int j, double v) { dst[j] = v; }, tb.inv_tw + (size_t)pi * N, m, tb.ninv[pi]);
+  ntt_inv_in<LOGN>(s, [&](int t) { return src[t]; }, tb.inv_tw + (size_t)pi * N, tb.perm, m, tb.ninv[pi],
+                   [&](int j, double v) { dst[j] = v; });
 }
 
 // signed integer coefficients [count][N] -> evaluation-domain residues
@@ -49,8 +51,9 @@ NTT_KERNEL(LOGN) void k_import_i64(const int64_t* __restrict__ in, double* __res
   const ModQ m = tb.mods[pi];
   const double t32 = tb.two32[pi];
   const int64_t* src = in + (size_t)c * N;
-  ntt_fwd<LOGN>(s, [&](int j) { return i64_to_res(src[j], m, t32); }, tb.fwd_tw + (size_t)pi * N, m);
-  store_orbit<LOGN>(s, out + (size_t)b * N, tb.perm);
+  double* dst = out + (size_t)b * N;
+  ntt_fwd_out<LOGN>(s, [&](int j) { return i64_to_res(src[j], m, t32); }, tb.fwd_tw + (size_t)pi * N, tb.perm, m,
+                    [&](int t, double v) { dst[t] = v; });
 }
 
 // evaluation-domain residues -> canonical coefficient residues as uint64
@@ -60,10 +63,10 @@ NTT_KERNEL(LOGN) void k_export_u64(const double* __restrict__ in, uint64_t* __re
   NTT_LDS(LOGN);
   const int b = blockIdx.x, pi = map.idx[b % map.n];
   const ModQ m = tb.mods[pi];
-  lds_from_orbit<LOGN>(s, in + (size_t)b * N, tb.perm, m);
+  const double* src = in + (size_t)b * N;
   uint64_t* dst = out + (size_t)b * N;
-  ntt_inv<LOGN>(s, [&](int j, double v) { dst[j] = f64_to_u64(canon(v, m)); }, tb.inv_tw + (size_t)pi * N, m,
-                tb.ninv[pi]);
+  ntt_inv_in<LOGN>(s, [&](int t) { return src[t]; }, tb.inv_tw + (size_t)pi * N, tb.perm, m, tb.ninv[pi],
+                   [&](int j, double v) { dst[j] = f64_to_u64(canon(v, m)); });
 }
 
 // ---------------------------------------------------------------------------
@@ -76,9 +79,9 @@ NTT_KERNEL(LOGN) void k_keygen(uint64_t seed, double* __restrict__ sk, DevTabs t
   NTT_LDS(LOGN);
   const int pi = blockIdx.x;
   const ModQ m = tb.mods[pi];
-  ntt_fwd<LOGN>(s, [&](int j) { return (double)sample_ternary(seed, kStreamSecret, (uint64_t)j); },
-                tb.fwd_tw + (size_t)pi * N, m);
-  store_orbit<LOGN>(s, sk + (size_t)pi * N, tb.perm);
+  double* dst = sk + (size_t)pi * N;
+  ntt_fwd_out<LOGN>(s, [&](int j) { return (double)sample_ternary(seed, kStreamSecret, (uint64_t)j); },
+                    tb.fwd_tw + (size_t)pi * N, tb.perm, m, [&](int t, double v) { dst[t] = v; });
 }
 
 // secret-key encryption of integer coefficients m (c1 = a, c0 = -a s + m + e)
@@ -87,7 +90,7 @@ NTT_KERNEL(LOGN) void k_keygen(uint64_t seed, double* __restrict__ sk, DevTabs t
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_encrypt(const int64_t* __restrict__ msg, const double* __restrict__ sk, uint64_t seed0,
                                  int lv, double* __restrict__ ct_all, double* const* __restrict__ ct_tab, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PER = N / T;
+  constexpr int N = 1 << LOGN;
   NTT_LDS(LOGN);
   const int i = blockIdx.x % (lv + 1), c = blockIdx.x / (lv + 1);
   const uint64_t seed = seed0 + (uint64_t)c;
@@ -95,28 +98,18 @@ NTT_KERNEL(LOGN) void k_encrypt(const int64_t* __restrict__ msg, const double* _
   double* ct = ct_tab ? ct_tab[c] : ct_all + (size_t)c * 2 * (lv + 1) * N;
   const ModQ m = tb.mods[i];
   const uint64_t qi = (uint64_t)m.q;
-  // a, sampled in the coefficient domain
-  ntt_fwd<LOGN>(s, [&](int j) { return sample_uniform_res(seed, kStreamEncA | (uint64_t)i, j, qi); },
-                tb.fwd_tw + (size_t)i * N, m);
   double* c0 = ct + (size_t)i * N;
   double* c1 = ct + (size_t)(lv + 1 + i) * N;
-  double areg[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int t = threadIdx.x + u * T;
-    areg[u] = s[lds_pad(tb.perm[t])];
-    c1[t] = areg[u];
-  }
+  // a, sampled in the coefficient domain
+  ntt_fwd_out<LOGN>(s, [&](int j) { return sample_uniform_res(seed, kStreamEncA | (uint64_t)i, j, qi); },
+                    tb.fwd_tw + (size_t)i * N, tb.perm, m, [&](int t, double v) { c1[t] = v; });
   const double t32 = tb.two32[i];
-  ntt_fwd<LOGN>(s, [&](int j) {
-      return reduce(i64_to_res(mc[j], m, t32) + (double)sample_cbd21(seed, kStreamEncE, (uint64_t)j), m);
-    }, tb.fwd_tw + (size_t)i * N, m);
   const double* sk_i = sk + (size_t)i * N;
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int t = threadIdx.x + u * T;
-    c0[t] = reduce(s[lds_pad(tb.perm[t])] - mulmod(areg[u], sk_i[t], m), m);
-  }
+  // c0 = m + e - a s; slot t of a is read back from what this thread wrote above
+  ntt_fwd_out<LOGN>(s, [&](int j) {
+      return reduce(i64_to_res(mc[j], m, t32) + (double)sample_cbd21(seed, kStreamEncE, (uint64_t)j), m);
+    }, tb.fwd_tw + (size_t)i * N, tb.perm, m,
+    [&](int t, double v) { c0[t] = reduce(v - mulmod(c1[t], sk_i[t], m), m); });
 }
 
 // c0 + c1 s -> canonical coefficient residues (uint64), block i = limb i
@@ -130,11 +123,9 @@ NTT_KERNEL(LOGN) void k_decrypt_u64(const double* __restrict__ ct, const double*
   const double* c0 = ct + (size_t)i * N;
   const double* c1 = ct + (size_t)(lv + 1 + i) * N;
   const double* sk_i = sk + (size_t)i * N;
-  for (int t = threadIdx.x; t < N; t += T) s[lds_pad(tb.perm[t])] = reduce(c0[t] + mulmod(c1[t], sk_i[t], m), m);
-  __syncthreads();
   uint64_t* dst = out + (size_t)i * N;
-  ntt_inv<LOGN>(s, [&](int j, double v) { dst[j] = f64_to_u64(canon(v, m)); }, tb.inv_tw + (size_t)i * N, m,
-                tb.ninv[i]);
+  ntt_inv_in<LOGN>(s, [&](int t) { return c0[t] + mulmod(c1[t], sk_i[t], m); }, tb.inv_tw + (size_t)i * N, tb.perm,
+                   m, tb.ninv[i], [&](int j, double v) { dst[j] = f64_to_u64(canon(v, m)); });
 }
 
 // c0 + c1 s -> canonical coefficient residues (binary64), for the CRT decoder;
@@ -150,10 +141,9 @@ NTT_KERNEL(LOGN) void k_decrypt_f64(const double* __restrict__ ct, const double*
   const double* c0 = base + (size_t)i * N;
   const double* c1 = base + (size_t)(lv + 1 + i) * N;
   const double* sk_i = sk + (size_t)i * N;
-  for (int t = threadIdx.x; t < N; t += T) s[lds_pad(tb.perm[t])] = reduce(c0[t] + mulmod(c1[t], sk_i[t], m), m);
-  __syncthreads();
   double* dst = out + ((size_t)c * (lv + 1) + i) * N;
-  ntt_inv<LOGN>(s, [&](int j, double v) { dst[j] = canon(v, m); }, tb.inv_tw + (size_t)i * N, m, tb.ninv[i]);
+  ntt_inv_in<LOGN>(s, [&](int t) { return c0[t] + mulmod(c1[t], sk_i[t], m); }, tb.inv_tw + (size_t)i * N, tb.perm,
+                   m, tb.ninv[i], [&](int j, double v) { dst[j] = canon(v, m); });
 }
 
 // Rotation (Galois) keys.  Block = (key kk, digit j, limb r of Q_L u P):
@@ -164,7 +154,7 @@ template <int LOGN>
 NTT_KERNEL(LOGN) void k_rotkey_gen(const double* __restrict__ sk, const int* __restrict__ rot_of_key,
                                     const uint32_t* __restrict__ galois_of_key, uint64_t seed, RotKeyArgs ka,
                                     double* __restrict__ keys, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PER = N / T;
+  constexpr int N = 1 << LOGN;
   NTT_LDS(LOGN);
   const int nlimb = ka.n_limbs;
   const int r = blockIdx.x % nlimb;
@@ -175,28 +165,21 @@ NTT_KERNEL(LOGN) void k_rotkey_gen(const double* __restrict__ sk, const int* __r
   const int rot = rot_of_key[kk];
   const uint64_t sa = kStreamKeyA | ((uint64_t)j << 40) | ((uint64_t)r << 24) | g;
   const uint64_t se = kStreamKeyE | ((uint64_t)j << 40) | g;
-  ntt_fwd<LOGN>(s, [&](int k) { return sample_uniform_res(seed, sa, k, (uint64_t)m.q); }, tb.fwd_tw + (size_t)r * N, m);
   double* kb = keys + ((((size_t)kk * ka.beta + j) * 2 + 0) * nlimb + r) * N;
   double* kaout = keys + ((((size_t)kk * ka.beta + j) * 2 + 1) * nlimb + r) * N;
-  double areg[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int t = threadIdx.x + u * T;
-    areg[u] = s[lds_pad(tb.perm[t])];
-    kaout[t] = areg[u];
-  }
-  ntt_fwd<LOGN>(s, [&](int k) { return (double)sample_cbd21(seed, se, (uint64_t)k); }, tb.fwd_tw + (size_t)r * N, m);
+  ntt_fwd_out<LOGN>(s, [&](int k) { return sample_uniform_res(seed, sa, k, (uint64_t)m.q); },
+                    tb.fwd_tw + (size_t)r * N, tb.perm, m, [&](int t, double v) { kaout[t] = v; });
   const double* sk_r = sk + (size_t)r * N;
   const bool in_digit = (r < ka.n_q) && (r / ka.alpha == j);
   const double pmod = ka.P_mod[r];
   const int half = N / 2;
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int t = threadIdx.x + u * T;
-    double v = s[lds_pad(tb.perm[t])] - mulmod(areg[u], sk_r[t], m);
-    if (in_digit) v += mulmod(pmod, sk_r[orbit_shift(t, rot, half)], m);
-    kb[t] = reduce(v, m);
-  }
+  // b = e - a s (+ P phi_g(s) on the digit's own limbs); a read back from this thread's writes
+  ntt_fwd_out<LOGN>(s, [&](int k) { return (double)sample_cbd21(seed, se, (uint64_t)k); }, tb.fwd_tw + (size_t)r * N,
+                    tb.perm, m, [&](int t, double e) {
+                      double v = e - mulmod(kaout[t], sk_r[t], m);
+                      if (in_digit) v += mulmod(pmod, sk_r[orbit_shift(t, rot, half)], m);
+                      kb[t] = reduce(v, m);
+                    });
 }
 
 // ---------------------------------------------------------------------------
@@ -214,12 +197,11 @@ NTT_KERNEL(LOGN) void k_modup_intt(const double* __restrict__ ct, const double* 
   NTT_LDS(LOGN);
   const int i = blockIdx.x % (lv + 1), c = blockIdx.x / (lv + 1);
   const ModQ m = tb.mods[i];
-  const double* c1 = (ct_tab ? ct_tab[c] : ct + (size_t)c * ct_stride) + (size_t)(lv + 1) * N;
-  lds_from_orbit<LOGN>(s, c1 + (size_t)i * N, tb.perm, m);
+  const double* c1 = (ct_tab ? ct_tab[c] : ct + (size_t)c * ct_stride) + (size_t)(lv + 1 + i) * N;
   const double ih = kl->up_inv_hat[i];
   double* dst = y + ((size_t)c * (lv + 1) + i) * N;
-  ntt_inv<LOGN>(s, [&](int j, double v) { dst[j] = canon(mulmod(canon(v, m), ih, m), m); }, tb.inv_tw + (size_t)i * N,
-                m, tb.ninv[i]);
+  ntt_inv_in<LOGN>(s, [&](int t) { return c1[t]; }, tb.inv_tw + (size_t)i * N, tb.perm, m, tb.ninv[i],
+                   [&](int j, double v) { dst[j] = canon(mulmod(canon(v, m), ih, m), m); });
 }
 
 template <int LOGN>
@@ -242,12 +224,11 @@ NTT_KERNEL(LOGN) void k_modup_conv(const double* __restrict__ y, const double* _
     return;
   }
   const double* yc = y + (size_t)c * (lv + 1) * N;
-  ntt_fwd<LOGN>(s, [&](int j) {
+  ntt_fwd_out<LOGN>(s, [&](int j) {
       double acc = 0.0;
       for (int u = 0; u < task.nsrc; ++u) acc += mulmod(yc[(size_t)(task.src0 + u) * N + j], task.hat[u], m);
       return reduce(acc, m);
-    }, tb.fwd_tw + (size_t)pi * N, m);
-  store_orbit<LOGN>(s, dst, tb.perm);
+    }, tb.fwd_tw + (size_t)pi * N, tb.perm, m, [&](int t, double v) { dst[t] = v; });
 }
 
 // ---------------------------------------------------------------------------
@@ -266,12 +247,12 @@ NTT_KERNEL(LOGN) void k_moddown_p(const double* __restrict__ u, const KsLevel* _
   const int k = blockIdx.x % alpha, x = blockIdx.x / alpha;
   const int pi = kl->n_q_total + k;
   const ModQ m = tb.mods[pi];
-  lds_from_orbit<LOGN>(s, u + ((size_t)x * K + lv + 1 + k) * N, tb.perm, m);
+  const double* src = u + ((size_t)x * K + lv + 1 + k) * N;
   const double h = kl->down_half[lv + 1 + k];
   const double ih = kl->down_inv_hat[k];
   double* dst = y + ((size_t)x * alpha + k) * N;
-  ntt_inv<LOGN>(s, [&](int c, double v) { dst[c] = canon(mulmod(canon(v + h, m), ih, m), m); },
-                tb.inv_tw + (size_t)pi * N, m, tb.ninv[pi]);
+  ntt_inv_in<LOGN>(s, [&](int t) { return src[t]; }, tb.inv_tw + (size_t)pi * N, tb.perm, m, tb.ninv[pi],
+                   [&](int c, double v) { dst[c] = canon(mulmod(canon(v + h, m), ih, m), m); });
 }
 
 template <int LOGN>
@@ -285,15 +266,14 @@ NTT_KERNEL(LOGN) void k_moddown_q(const double* __restrict__ u, const double* __
   const ModQ m = tb.mods[i];
   const double h = kl->down_half[i];
   const double* yx = y + (size_t)x * alpha * N;
-  ntt_fwd<LOGN>(s, [&](int c) {
-      double acc = -h;
-      for (int k = 0; k < alpha; ++k) acc += mulmod(yx[(size_t)k * N + c], kl->down_hat[k * kMaxLimbs + i], m);
-      return reduce(acc, m);
-    }, tb.fwd_tw + (size_t)i * N, m);
   const double pinv = kl->down_pinv[i];
   const double* ui = u + ((size_t)x * K + i) * N;
   double* oi = out_tab ? out_tab[x >> 1] + ((size_t)(x & 1) * (lv + 1) + i) * N : out + ((size_t)x * (lv + 1) + i) * N;
-  for (int t = threadIdx.x; t < N; t += T) oi[t] = reduce(mulmod(ui[t] - s[lds_pad(tb.perm[t])], pinv, m), m);
+  ntt_fwd_out<LOGN>(s, [&](int c) {
+      double acc = -h;
+      for (int k = 0; k < alpha; ++k) acc += mulmod(yx[(size_t)k * N + c], kl->down_hat[k * kMaxLimbs + i], m);
+      return reduce(acc, m);
+    }, tb.fwd_tw + (size_t)i * N, tb.perm, m, [&](int t, double v) { oi[t] = reduce(mulmod(ui[t] - v, pinv, m), m); });
 }
 
 // Rescale by q_lv (drop the last limb, coefficient-wise rounding) on `npoly`
@@ -301,24 +281,24 @@ NTT_KERNEL(LOGN) void k_moddown_q(const double* __restrict__ u, const double* __
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_rescale(const double* __restrict__ in, int lv, const RescaleArgs ra, double* __restrict__ out,
                                  DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
+  constexpr int N = 1 << LOGN, PER = NttShape<LOGN>::PER;
   NTT_LDS(LOGN);
   const int i = blockIdx.x % lv, x = blockIdx.x / lv;
   const ModQ ml = tb.mods[lv];
   const ModQ m = tb.mods[i];
   // INTT of the dropped limb (every block recomputes it; the limb is L2-resident)
-  lds_from_orbit<LOGN>(s, in + ((size_t)x * (lv + 1) + lv) * N, tb.perm, ml);
-  double c[16];
-  ntt_inv_regs<LOGN>(s, c, tb.inv_tw + (size_t)lv * N, ml, tb.ninv[lv]);
+  const double* last = in + ((size_t)x * (lv + 1) + lv) * N;
+  double c[PER];
+  ntt_inv_in_regs<LOGN>(s, [&](int t) { return last[t]; }, tb.inv_tw + (size_t)lv * N, tb.perm, ml, tb.ninv[lv], c);
   const double hl = ra.half_mod_last, hi = ra.half_mod[i];
   // [c + h]_{q_l} lifted to q_i, minus h mod q_i
 #pragma unroll
-  for (int w = 0; w < 16; ++w) c[w] = reduce(canon(c[w] + hl, ml) - hi, m);
-  ntt_fwd_regs<LOGN>(s, c, tb.fwd_tw + (size_t)i * N, m);
+  for (int w = 0; w < PER; ++w) c[w] = reduce(canon(c[w] + hl, ml) - hi, m);
   const double inv = ra.inv_last[i];
   const double* ui = in + ((size_t)x * (lv + 1) + i) * N;
   double* oi = out + ((size_t)x * lv + i) * N;
-  for (int t = threadIdx.x; t < N; t += T) oi[t] = reduce(mulmod(ui[t] - s[lds_pad(tb.perm[t])], inv, m), m);
+  ntt_fwd_regs_out<LOGN>(s, c, tb.fwd_tw + (size_t)i * N, tb.perm, m,
+                         [&](int t, double v) { oi[t] = reduce(mulmod(ui[t] - v, inv, m), m); });
 }
 
 // ---------------------------------------------------------------------------
@@ -531,6 +511,7 @@ static void launch_ntt_all(const LaunchCtx& L, NttOp op, const void* in, void* o
     case 12: FN<12>(__VA_ARGS__); break;                  \
     case 13: FN<13>(__VA_ARGS__); break;                  \
     case 14: FN<14>(__VA_ARGS__); break;                  \
+    case 15: FN<15>(__VA_ARGS__); break;                  \
     default: return hipErrorInvalidValue;                 \
   }
 

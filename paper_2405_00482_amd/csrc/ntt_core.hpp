@@ -39,9 +39,13 @@ struct DevTabs {
 template <int LOGN>
 struct NttShape {
   static constexpr int N = 1 << LOGN;
-  static constexpr int T = N / 16;              // threads per workgroup
-  static constexpr int LDS = N + N / 16;        // padded LDS doubles
-  static constexpr int S0 = LOGN - 12;          // stages of the leading (large-span) pass
+  // log2 of the transform held in LDS at once: the whole limb up to 2^14; a
+  // 2^15 limb (256 KiB) is done as one radix-2 stage plus two 2^14 halves
+  static constexpr int LOGH = LOGN < 15 ? LOGN : 14;
+  static constexpr int T = (1 << LOGH) / 16;    // threads per workgroup
+  static constexpr int PER = N / T;             // coefficients per thread: 16, or 32 at 2^15
+  static constexpr int LDS = (1 << LOGH) + (1 << LOGH) / 16;  // padded LDS doubles
+  static constexpr int S0 = LOGH - 12;          // stages of the leading (large-span) pass
 };
 
 __device__ __forceinline__ int lds_pad(int j) { return j + (j >> 4); }
@@ -254,6 +258,99 @@ __device__ __forceinline__ void lds_from_orbit(double* s, const double* __restri
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
   for (int t = threadIdx.x; t < N; t += T) s[lds_pad(perm[t])] = reduce(in[t], m);
   __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Size-generic entry points.  Thread tid owns coefficients j = tid + w*T,
+// w < PER, and the evaluation-domain (orbit-order) slots t = tid + u*T.
+//
+// At N = 2^15 the limb does not fit in LDS.  The forward transform's first
+// Cooley-Tukey stage pairs j and j + N/2, which the same thread owns (w and
+// w + 16), so it runs in registers; the two halves are then independent 2^14
+// transforms whose twiddles are the full table's entries re-indexed per half
+// (the host stores half h's table at offset h * 2^14 of the prime's row and
+// the first stage's twiddle at index 0, unused by the 2^14 transform).  The
+// bit-reversed half h holds exactly the orbit slots [h N/2, (h+1) N/2) (odd
+// exponents 5^t are 1 mod 4, -5^t are 3 mod 4), so each half is written out
+// contiguously.  The inverse runs the two halves' Gentleman-Sande stages in
+// LDS one after the other and their last stage (span N/2) in registers.
+// ---------------------------------------------------------------------------
+template <int LOGN, class Out>
+__device__ __forceinline__ void ntt_fwd_regs_out(double* s, const double (&c)[NttShape<LOGN>::PER],
+                                                 const double* __restrict__ tw, const uint32_t* __restrict__ perm,
+                                                 ModQ m, Out out) {
+  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
+  if constexpr (LOGN <= 14) {
+    ntt_fwd_regs<LOGN>(s, c, tw, m);
+    for (int t = threadIdx.x; t < N; t += T) out(t, s[lds_pad(perm[t])]);
+  } else {
+    constexpr int H = 1 << 14;
+    const double w0 = tw[0];
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      double x[16];
+#pragma unroll
+      for (int w = 0; w < 16; ++w) {
+        const double U = reduce(c[w], m), V = mulmod(c[w + 16], w0, m);
+        x[w] = h ? U - V : U + V;
+      }
+      ntt_fwd_regs<14>(s, x, tw + h * H, m);
+      for (int t = h * (N / 2) + (int)threadIdx.x; t < (h + 1) * (N / 2); t += T) out(t, s[lds_pad(perm[t] - h * H)]);
+    }
+  }
+}
+
+// forward transform of the coefficients load(j), handing slot t to out(t, v)
+template <int LOGN, class Load, class Out>
+__device__ __forceinline__ void ntt_fwd_out(double* s, Load load, const double* __restrict__ tw,
+                                            const uint32_t* __restrict__ perm, ModQ m, Out out) {
+  constexpr int T = NttShape<LOGN>::T, PER = NttShape<LOGN>::PER;
+  double c[PER];
+#pragma unroll
+  for (int w = 0; w < PER; ++w) c[w] = load((int)threadIdx.x + w * T);
+  ntt_fwd_regs_out<LOGN>(s, c, tw, perm, m, out);
+}
+
+// Inverse transform of the orbit-order values in(t) (|x| < 2^51); c[w] gets
+// coefficient tid + w*T times N^-1, centred.  LDS may still be read by other
+// threads on return: barrier before writing `s` again.
+template <int LOGN, class In>
+__device__ __forceinline__ void ntt_inv_in_regs(double* s, In in, const double* __restrict__ itw,
+                                                const uint32_t* __restrict__ perm, ModQ m, double ninv,
+                                                double (&c)[NttShape<LOGN>::PER]) {
+  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
+  if constexpr (LOGN <= 14) {
+    for (int t = threadIdx.x; t < N; t += T) s[lds_pad(perm[t])] = reduce(in(t), m);
+    __syncthreads();
+    ntt_inv_regs<LOGN>(s, c, itw, m, ninv);
+  } else {
+    constexpr int H = 1 << 14;
+    double c0[16], c1[16];
+    for (int t = threadIdx.x; t < N / 2; t += T) s[lds_pad(perm[t])] = reduce(in(t), m);
+    __syncthreads();
+    ntt_inv_regs<14>(s, c0, itw, m, ninv);
+    __syncthreads();
+    for (int t = N / 2 + (int)threadIdx.x; t < N; t += T) s[lds_pad(perm[t] - H)] = reduce(in(t), m);
+    __syncthreads();
+    ntt_inv_regs<14>(s, c1, itw + H, m, ninv);
+    const double iw0 = itw[0];
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      c[w] = reduce(c0[w] + c1[w], m);
+      c[w + 16] = reduce(mulmod(c0[w] - c1[w], iw0, m), m);
+    }
+  }
+}
+
+// inverse transform of in(t), handing coefficient j to store(j, v)
+template <int LOGN, class In, class Store>
+__device__ __forceinline__ void ntt_inv_in(double* s, In in, const double* __restrict__ itw,
+                                           const uint32_t* __restrict__ perm, ModQ m, double ninv, Store store) {
+  constexpr int T = NttShape<LOGN>::T, PER = NttShape<LOGN>::PER;
+  double c[PER];
+  ntt_inv_in_regs<LOGN>(s, in, itw, perm, m, ninv, c);
+#pragma unroll
+  for (int w = 0; w < PER; ++w) store((int)threadIdx.x + w * T, c[w]);
 }
 
 }  // namespace pvfl

@@ -121,7 +121,7 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
         I.n_rot = 0;
         I.n_hstrot = (int64_t)I.col_blocks * (I.mprime - 1);
         I.n_modup = I.mprime > 1 ? I.col_blocks : 0;
-        I.n_moddown = lazy ? (I.mprime > 1 ? I.row_blocks : 0) : (int)I.n_hstrot * I.row_blocks;
+        I.n_moddown = lazy ? (I.mprime > 1 || c->alpha > 1 ? I.row_blocks : 0) : (int)I.n_hstrot * I.row_blocks;
       }
       break;
     }
@@ -148,7 +148,7 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
       I.n_add = nd - 1 + I.n_rot;
       I.n_hstrot = nd - 1;
       I.n_modup = (nd > 1 ? 1 : 0) + (int)I.n_rot;
-      I.n_moddown = (lazy ? (nd > 1 ? 1 : 0) : nd - 1) + (int)I.n_rot;
+      I.n_moddown = (lazy ? (nd > 1 || c->alpha > 1 ? 1 : 0) : nd - 1) + (int)I.n_rot;
       break;
     }
     case PVFL_PLAN_ROW: {
@@ -321,9 +321,11 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
   double* rct = v + (bs ? 2 * Q : 0);                   // BSGS: phi(c0) [lv+1][N]
   LaunchCtx L = launch_ctx(c, stream);
   const int mprime = p->info.mprime;
-  if (mprime == 1) {
-    // no rotation: ModDown(P * c * pt) is c * pt exactly, so skip Q u P
-    // (the Q limbs of a Q u P plaintext come first)
+  if (mprime == 1 && c->alpha == 1) {
+    // no rotation and one special prime: ModDown(P * c * pt) is c * pt exactly
+    // (the base conversion of a single residue is exact), so skip Q u P; the
+    // Q limbs of a Q u P plaintext come first.  With alpha > 1 the fast base
+    // conversion may add P, and the Q u P form's result differs by one.
     for (int b = 0; b < RB; ++b) {
       double* ob = out + (size_t)b * 2 * Q;
       HIP_TRY(launch_fill_zero(L, ob, 2 * Q));

@@ -52,6 +52,8 @@ def _same(a, b, what):
     ("C1", [(16, 256), (100, 37), (64, 64), (8, 2048)], 4, 64, 2),
     ("C3", W.c3_shapes(64)[:6], 4, 16, 2),
     ("C3", W.c3_shapes(64)[:6], 1, 1024, 1),
+    ("C4", [(16, 256), (3, 5), (300, 700)], 2, 32, 2),     # three special primes, two digits
+    ("C5", [(16, 4096), (3, 5), (40, 1000)], 2, 32, 1),    # ring 2^15, split transforms
 ])
 def test_batch_equals_percall(name, shapes, group, chunk, vec):
     ctx, sk, plans, keys, X, v, bufs = _setup(name, shapes)

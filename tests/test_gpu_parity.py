@@ -15,10 +15,12 @@ pytestmark = pytest.mark.gpu
 SEED_SK, SEED_KEYS, SEED_ENC = 11, 12, 13
 
 
-@pytest.fixture(scope="module")
-def c1():
-    prm = O.Params.from_dict(W.params_dict("C1"))
-    ctx = context("C1")
+@pytest.fixture(scope="module", params=["C1", "C5"])
+def c1(request):
+    """a ring-2^12 and a ring-2^15 parameter set (the latter's limbs exceed LDS
+    and take the split transform)"""
+    prm = O.Params.from_dict(W.params_dict(request.param))
+    ctx = context(request.param)
     sk_gpu = ctx.keygen(SEED_SK)
     s = O.keygen(prm, SEED_SK)
     return prm, ctx, sk_gpu, s
@@ -208,6 +210,18 @@ def test_hybrid_partition_and_ragged(m, n):
     X = rng.uniform(-1, 1, (m, n))
     y = rng.uniform(-1, 1, n)
     run_hybrid_both("C1", X, y, True)
+
+
+@pytest.mark.parametrize("name,m,n,lazy", [("C5", 16, 4096, True), ("C5", 16, 4096, False), ("C5", 3, 5, True)])
+def test_hybrid_ring_2_15_bit_exact(name, m, n, lazy):
+    """hybrid product at N = 2^15 (10 limbs over Q u P, 4 digits): residues equal the oracle's"""
+    rng = np.random.default_rng(m + n)
+    X = rng.uniform(-1, 1, (m, n))
+    y = rng.uniform(-1, 1, n)
+    prm, s, outs, oplan = run_hybrid_both(name, X, y, lazy)
+    z = O.decrypt_decode(prm, s, outs[0], prm.scale ** 2)
+    got = PL.hybrid_lazy_ras(oplan, [z])
+    assert np.linalg.norm(got - X @ y) / np.linalg.norm(X @ y) < 2.0 ** -20
 
 
 @pytest.mark.parametrize("m,n,bs", [(64, 256, 2), (64, 256, 4), (100, 37, 2), (4096, 64, 8), (64, 4096, 4)])

@@ -25,7 +25,7 @@ def signed_diff(a, b, q):
 
 
 @pytest.mark.parametrize("name,m,n,bs", [("C1", 16, 256, 0), ("C2", 256, 1024, 0), ("C1", 100, 37, 0),
-                                         ("C2", 256, 1024, 8)])
+                                         ("C2", 256, 1024, 8), ("C5", 40, 1000, 0)])
 def test_encode_pt_within_one_of_oracle(name, m, n, bs):
     prm = O.Params.from_dict(W.params_dict(name))
     ctx = context(name)
@@ -163,3 +163,36 @@ def test_ctmat_real_path(pack):
         ref = A @ B
         err = np.linalg.norm(y.cpu().numpy().reshape(m, nout) - ref) / np.linalg.norm(ref)
         assert err < 2.0 ** -20, err
+
+
+def test_ring_2_15_full_size_product():
+    """The large workload at full size: X^T (5000 x 4096, 90% zeros) times one
+    encrypted column of R at N = 2^15 with 8+2 primes -- m' = 2048, 2047
+    hoisted rotations over a 40 GiB key set.  The decrypted product must be
+    within 2^-20 of the FP64 product (every output, norm-wise)."""
+    t = torch()
+    name = "C5"
+    ctx = context(name)
+    XT, R = W.c5_inputs(cols=[0])
+    r = np.ascontiguousarray(R[:, 0])
+    m, n = XT.shape
+    plan = ctx.plan(0, m, n, lazy=True)
+    assert plan.info["mprime"] == 2048 and plan.info["n_galois"] == 2047
+    seeds = W.seeds(name)
+    sk = ctx.keygen(seeds["sk"])
+    keys = ctx.rotkeys(sk, plan.galois(), seeds["rotkeys"])
+    pt = dev_f64(plan.bytes("pt") // 8)
+    ct = dev_f64(plan.bytes("ct_in") // 8)
+    out = dev_f64(plan.bytes("ct_out") // 8)
+    y = dev_f64(m)
+    plan.encode_pt(to_dev(XT), pt)
+    plan.encrypt(sk, to_dev(r), seeds["enc"], ct)
+    plan.matmul(ct, pt, keys, out)
+    plan.decrypt_decode(sk, out, y)
+    got = y.cpu().numpy()
+    ref = XT @ r
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"C5 full size: rel err 2^{np.log2(err):.2f}")
+    assert err < 2.0 ** -20
+    del keys
+    t.cuda.empty_cache()
