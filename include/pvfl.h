@@ -238,6 +238,21 @@ pvfl_status pvfl_batch_run(pvfl_batch* batch, const pvfl_sk* sk, uint64_t seed, 
 pvfl_status pvfl_batch_info(const pvfl_batch* batch, int64_t* n_work_items, double* key_bytes, double* pt_bytes);
 void pvfl_batch_destroy(pvfl_batch* batch);
 
+/* Transposed diagonal conversion (Sec. 5.3, Eq. 7).  plan: a CTMAT plan of
+ * [[A]] (m x n) with pack * max(m_pad, n_pad) = N/2, so that every slot block
+ * holds the diagonal and a rotation is cyclic over max(m, n).  ct_in: the
+ * plan's input ciphertexts (min(m, n) Eq. 5 diagonals of A); ct_out (same
+ * size, not overlapping ct_in) receives the Eq. 5 diagonals of A^T, the
+ * input of a CTMAT plan of shape n x m with the same pack.  Diagonal i of A^T
+ * is diagonal k of A rotated left by r (unhoisted rotation): with
+ * lo = min(m_pad, n_pad), k = (lo - i) mod lo and r = i when m_pad >= n_pad,
+ * r = max - lo + i (0 for i = 0) otherwise -- the printed equation's RotR by
+ * max - min + i does not reproduce A^T for tall matrices.
+ * pvfl_ctmat_transpose_galois lists the Galois elements the keys must hold. */
+pvfl_status pvfl_ctmat_transpose_galois(const pvfl_plan* plan, uint32_t* out, int32_t cap, int32_t* count);
+pvfl_status pvfl_ctmat_transpose(const pvfl_plan* plan, const void* ct_in, const pvfl_rotkeys* keys, void* ct_out,
+                                 void* stream);
+
 /* Latency-model network of the plan selector: a 3-layer perceptron
  * y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 in FP32 (n_in <= 64 inputs,
  * hidden <= 64), trained on measured plan latencies by hand-written HIP
@@ -259,34 +274,47 @@ pvfl_status pvfl_mlp_train_step(pvfl_mlp* mlp, const float* x_dev, const float* 
                                 float* loss_dev, void* stream);
 void pvfl_mlp_destroy(pvfl_mlp* mlp);
 
-/* Plan selection.  For X (m x n) times an encrypted vector at `level`, the
- * candidates are every valid HYBRID / DIAG / ROW plan with lazy or
- * per-rotation ModDown and every baby-step size (Sec. 3-4; Tables 2 and 3
- * give their operation counts).
- * pvfl_plan_candidates: writes up to cap option sets, *count = how many exist.
- * pvfl_plan_features: the PVFL_PLAN_FEATURES-long feature vector of a plan
- *   (log2 N, l+1, alpha, beta, K, log2 m, log2 n, log2 m', kind one-hot, lazy,
- *   in-ciphertext RaS, BSGS flag and log2 b, log2(1+count) of Mult, Add, Rot,
- *   HstRot, ModUp, ModDown, encoded limbs, keys, blocks).
+/* Plan selection.  Two operand forms (Sec. 5):
+ *   PVFL_OPERAND_CT_VEC: X (m x n, plaintext) times an encrypted vector.  The
+ *     candidates are every valid HYBRID / DIAG / ROW plan with lazy or
+ *     per-rotation ModDown and every baby-step size (Sec. 3-4), batch 1.
+ *   PVFL_OPERAND_CT_MAT: [[A]] (m x n, encrypted) times W (n x n_out).  The
+ *     candidates are Alg. 3 (CTMAT) with every column-packing factor, batch 1,
+ *     and the per-row form: W^T times each encrypted row of A as a lazy
+ *     HYBRID or DIAG plan of shape n_out x n, batch m, sharing one set of
+ *     plaintexts.
+ * pvfl_plan_candidates: writes up to cap candidates, *count = how many exist.
+ * pvfl_plan_features: the PVFL_PLAN_FEATURES-long feature vector of a plan run
+ *   `batch` times (log2 N, l+1, alpha, beta, K, log2 m, log2 n, log2 m', kind
+ *   one-hot (HYBRID, DIAG, ROW, CTMAT), lazy, in-ciphertext RaS, BSGS flag and
+ *   log2 b, log2 pack, log2 batch, log2(1+count) of Mult, Add, Rot, HstRot,
+ *   ModUp, ModDown (per product), encoded limbs, keys, blocks).
  * pvfl_plan_analytic_ms: sum over the PVFL_COST_TERMS counts (Mult, Add, Rot,
- *   HstRot, ModUp, ModDown, encoded plaintext limbs, 1) of count x costs[i].
+ *   HstRot, ModUp, ModDown -- each times batch -- encoded plaintext limbs, 1)
+ *   of count x costs[i].
  * pvfl_planner_create: a learned latency model -- a pvfl_mlp over features
  *   standardised by (x - x_mean) / x_std predicting (ln ms - y_mean) / y_std.
  *   The network is borrowed and must outlive the planner.
  * pvfl_plan_choose: the candidate of least predicted latency, by the network
  *   when costs is NULL, else by the analytic model.  Synchronises `stream`. */
-#define PVFL_PLAN_FEATURES 24
+#define PVFL_PLAN_FEATURES 27
 #define PVFL_COST_TERMS 8
+enum { PVFL_OPERAND_CT_VEC = 0, PVFL_OPERAND_CT_MAT = 1 };
+typedef struct {
+  pvfl_plan_opts opts;
+  int32_t batch;  /* products the candidate runs with these options (rows of A for the per-row form) */
+} pvfl_candidate;
 typedef struct pvfl_planner pvfl_planner;
-pvfl_status pvfl_plan_candidates(pvfl_ctx* ctx, int32_t m, int32_t n, int32_t level, pvfl_plan_opts* out, int32_t cap,
-                                 int32_t* count);
+pvfl_status pvfl_plan_candidates(pvfl_ctx* ctx, int32_t operand, int32_t m, int32_t n, int32_t n_out, int32_t level,
+                                 pvfl_candidate* out, int32_t cap, int32_t* count);
 int32_t pvfl_plan_num_features(void);
-pvfl_status pvfl_plan_features(const pvfl_plan* plan, float* out, int32_t cap);
-pvfl_status pvfl_plan_analytic_ms(const pvfl_plan* plan, const double* costs, double* ms);
+pvfl_status pvfl_plan_features(const pvfl_plan* plan, int32_t batch, float* out, int32_t cap);
+pvfl_status pvfl_plan_analytic_ms(const pvfl_plan* plan, int32_t batch, const double* costs, double* ms);
 pvfl_status pvfl_planner_create(pvfl_mlp* mlp, const float* x_mean, const float* x_std, float y_mean, float y_std,
                                 pvfl_planner** out);
-pvfl_status pvfl_plan_choose(pvfl_planner* planner, pvfl_ctx* ctx, int32_t m, int32_t n, int32_t level,
-                             const double* costs, pvfl_plan_opts* chosen, double* predicted_ms, void* stream);
+pvfl_status pvfl_plan_choose(pvfl_planner* planner, pvfl_ctx* ctx, int32_t operand, int32_t m, int32_t n,
+                             int32_t n_out, int32_t level, const double* costs, pvfl_candidate* chosen,
+                             double* predicted_ms, void* stream);
 void pvfl_planner_destroy(pvfl_planner* planner);
 
 /* Optional kernel timing for measurement.  When enabled, every launch of the

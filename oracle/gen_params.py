@@ -43,6 +43,13 @@ def main():
         "C4": config("C4", 14, 5, 1, 3, 40.0),
         "C5": config("C5", 15, 7, 1, 2, 40.0),
     }
+    # C4 with fewer special primes (more key-switch digits): the plan selector's
+    # digit-count variants; same ciphertext primes, special primes a prefix of C4's
+    for a in (1, 2):
+        v = dict(cfgs["C4"])
+        v["name"] = f"C4a{a}"
+        v["p"] = cfgs["C4"]["p"][:a]
+        cfgs[v["name"]] = v
     # special primes must be ~2^48; for C1 take the largest below 2^48 as well
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                         "paper_2405_00482_amd", "params.json")

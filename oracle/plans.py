@@ -589,3 +589,47 @@ def ctmat_matmul(params: O.Params, plan: CtMatPlan, cts, pt_ints) -> list:
             acc = O.ct_add(params, acc, O.ct_mul_pt(params, cts[i], pt))
         outs.append(acc)
     return outs
+
+
+# ---------------------------------------------------------------------------
+# Transposed diagonal conversion (Sec. 5.3, Eq. 7): the Eq. 5 diagonal
+# ciphertexts of A^T from those of A, one rotation each.  As printed (RotR of
+# diagonal (min - i) mod min by max - min + i) the equation does not
+# reproduce A^T's diagonals for any tall shape; the reading below follows from
+# e_k[j] = A[j mod m, (k + j) mod n] with the slots cyclic over max(m, n):
+#   m >= n:  e'_i = RotL(e_((n - i) mod n), i)
+#   m <  n:  e'_i = RotL(e_((m - i) mod m), n - m + i)  (i > 0),  e'_0 = e_0
+# Rotating over all N' slots is cyclic over max(m, n) only when every block
+# holds the diagonal, i.e. pack * max(m, n) = N'.
+# ---------------------------------------------------------------------------
+def transpose_map(plan: CtMatPlan) -> list:
+    """(k, r) for every diagonal i of A^T: e'_i = RotL(e_k, r)"""
+    lo, hi = plan.ndiag, plan.width
+    out = []
+    for i in range(lo):
+        k = (lo - i) % lo
+        if plan.mp >= plan.np_:
+            r = i
+        else:
+            r = 0 if i == 0 else hi - lo + i
+        out.append((k, r))
+    return out
+
+
+def transpose_map_as_printed(plan: CtMatPlan) -> list:
+    """Eq. 7 read literally (RotR by max - min + i), for the pin that rejects it"""
+    lo, hi = plan.ndiag, plan.width
+    return [((lo - i) % lo, -((hi - lo + i) % hi)) for i in range(lo)]
+
+
+def transpose_galois(plan: CtMatPlan, N: int) -> list:
+    return sorted(set(O.galois_rotl(r, N) for _, r in transpose_map(plan) if r))
+
+
+def ctmat_transpose(params: O.Params, plan: CtMatPlan, cts, keys: dict) -> list:
+    """diagonal ciphertexts of A^T from those of A (unhoisted rotations, O3)"""
+    assert plan.pack * plan.width == plan.slots, "the conversion needs every block to hold the diagonal"
+    out = []
+    for k, r in transpose_map(plan):
+        out.append(cts[k] if r == 0 else O.rotate(params, cts[k], keys[O.galois_rotl(r, params.N)]))
+    return out

@@ -84,7 +84,8 @@ struct pvfl_plan {
   // device tables
   int* iota_dev = nullptr;     // [max(mprime, 1)] = 0..mprime-1
   int* rot_dev = nullptr;      // BSGS: [mprime] baby rotation of diagonal i (i mod bsgs)
-  int chunk = 1, nchunk = 1;   // diagonal chunking of the fused kernel
+  int chunk = 1, nchunk = 1;   // diagonal chunking of the fused kernel (BSGS: nchunk = giant steps x chunks per step)
+  int chunks_per_giant = 1;    // BSGS: chunks of one giant step's inner sum
   // DIAG plan: in-ciphertext RaS rotations; ROW plan: per-row data
   std::vector<int> ras_rots;
   // private workspace when the caller passes none

@@ -350,13 +350,15 @@ __global__ __launch_bounds__(256) void k_diag_lazy(DiagArgs a) {
   part[(size_t)K * N + limbN + t] = reduce(acc1, m);
 }
 
-// sum the chunk partials: part[nchunk][2][K][N] -> acc[2][K][N]
+// sum the chunk partials of every group y: part[y][nchunk][2][K][N] -> acc[y][2][K][N]
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int nchunk, int K, int N,
                                                        LimbMap limb_prime, const ModQ* __restrict__ mods,
                                                        double* __restrict__ acc) {
   const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
   const size_t tot = (size_t)2 * K * N;
   if (idx >= tot) return;
+  part += (size_t)blockIdx.y * nchunk * tot;
+  acc += (size_t)blockIdx.y * tot;
   const int r = (int)((idx / N) % K);
   const ModQ m = mods[limb_prime.idx[r]];
   double v = 0.0;
@@ -623,10 +625,11 @@ hipError_t launch_diag_lazy(const LaunchCtx& L, const DiagArgs& a, int nchunk) {
 }
 
 hipError_t launch_sum_partials(const LaunchCtx& L, const double* part, int nchunk, int K, int N, LimbMap limb_prime,
-                               double* acc) {
+                               double* acc, int ngroups) {
   const size_t tot = (size_t)2 * K * N;
-  hipLaunchKernelGGL(k_sum_partials, dim3(blocks_for(tot)), dim3(256), 0, L.stream, part, nchunk, K, N, limb_prime,
-                     L.tb.mods, acc);
+  if (ngroups < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_partials, dim3(blocks_for(tot), ngroups), dim3(256), 0, L.stream, part, nchunk, K, N,
+                     limb_prime, L.tb.mods, acc);
   return hipGetLastError();
 }
 

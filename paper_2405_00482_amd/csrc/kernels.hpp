@@ -96,8 +96,9 @@ hipError_t launch_moddown(const LaunchCtx& L, const double* u, int npoly, int lv
                           double* y, double* out, double* const* out_tab = nullptr);
 hipError_t launch_rescale(const LaunchCtx& L, const double* in, int npoly, int lv, const RescaleArgs& ra, double* out);
 hipError_t launch_diag_lazy(const LaunchCtx& L, const DiagArgs& a, int nchunk);
+// part[y][nchunk][2][K][N] summed over the chunks into acc[y][2][K][N], y < ngroups
 hipError_t launch_sum_partials(const LaunchCtx& L, const double* part, int nchunk, int K, int N, LimbMap limb_prime,
-                               double* acc);
+                               double* acc, int ngroups = 1);
 // Alg. 3: out[k] = sum_i ct[i] * pt[i][k]   (ct [nct][2][lv+1][N], pt [nct][nout][lv+1][N])
 hipError_t launch_ctmat(const LaunchCtx& L, const double* ct, const double* pt, int nct, int nout, int lv, int N,
                         double* out);

@@ -208,9 +208,13 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
   if (hipMalloc((void**)&p->iota_dev, sizeof(int) * mprime) != hipSuccess) return fail(PVFL_E_NOMEM, "plan tables");
   HIP_TRY(hipMemcpy(p->iota_dev, iota.data(), sizeof(int) * mprime, hipMemcpyHostToDevice));
   if (I.bsgs) {
-    // one fused-kernel chunk per giant step: its partial is that step's inner sum
-    p->chunk = I.bsgs;
-    p->nchunk = mprime / I.bsgs;
+    // chunks never straddle a giant step; enough of them to fill the chip
+    const int g = mprime / I.bsgs;
+    int per = 1;
+    while (per < I.bsgs && (int64_t)g * per < target) per *= 2;
+    p->chunks_per_giant = per;
+    p->chunk = I.bsgs / per;
+    p->nchunk = g * per;
     for (int i = 0; i < mprime; ++i) iota[i] = i % I.bsgs;
     if (hipMalloc((void**)&p->rot_dev, sizeof(int) * mprime) != hipSuccess) return fail(PVFL_E_NOMEM, "plan tables");
     HIP_TRY(hipMemcpy(p->rot_dev, iota.data(), sizeof(int) * mprime, hipMemcpyHostToDevice));
@@ -254,10 +258,10 @@ static size_t ws_doubles(const pvfl_plan* p) {
     case PVFL_PLAN_HYBRID:
     case PVFL_PLAN_DIAG:
       if (p->opts.lazy_moddown) {
-        const size_t CB = p->info.col_blocks, g = p->info.bsgs ? p->nchunk : 1;
+        const size_t CB = p->info.col_blocks, g = p->info.bsgs ? p->nchunk / p->chunks_per_giant : 1;
         const size_t bsgs = p->info.bsgs ? g * 2 * Q + digits + 2 * Q + Q : 0;
         // + 4Q at the end: in-ciphertext RaS temporaries
-        return CB * digits + Q + CB * 2 * Q + CB * p->nchunk * 2 * KN + 2 * KN + g * ydown + bsgs + 4 * Q;
+        return CB * digits + Q + CB * 2 * Q + CB * p->nchunk * 2 * KN + g * 2 * KN + g * ydown + bsgs + 4 * Q;
       }
       return digits + Q + 2 * KN + ydown + 2 * Q + 4 * Q;
     case PVFL_PLAN_ROW:
@@ -305,7 +309,7 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
   pvfl_ctx* c = p->ctx;
   const int N = c->N, lv = p->lv, K = p->K;
   const int CB = p->info.col_blocks, RB = p->info.row_blocks;
-  const int bs = p->info.bsgs, g = bs ? p->nchunk : 1;
+  const int bs = p->info.bsgs, g = bs ? p->nchunk / p->chunks_per_giant : 1;
   const size_t Q = (size_t)(lv + 1) * N, KN = (size_t)K * N, DG = (size_t)p->beta * KN;
   const KsLevel& kl = c->ks_host[lv];
   // workspace, in the order ws_doubles counts it
@@ -313,8 +317,8 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
   double* yup = digits + CB * DG;                       // [lv+1][N]
   double* pc = yup + Q;                                 // [CB][2][lv+1][N]: P*c of every input
   double* part = pc + CB * 2 * Q;                       // [CB][nchunk][2][K][N]
-  double* acc = part + (size_t)CB * p->nchunk * 2 * KN; // [2][K][N]
-  double* ydown = acc + 2 * KN;                         // [2g][alpha][N]
+  double* acc = part + (size_t)CB * p->nchunk * 2 * KN; // [g][2][K][N]
+  double* ydown = acc + (size_t)g * 2 * KN;             // [2g][alpha][N]
   double* cj = ydown + (size_t)2 * g * c->alpha * N;    // BSGS: [g][2][lv+1][N] giant-step inner sums
   double* dig2 = cj + (bs ? g * 2 * Q : 0);             // BSGS: digits of one inner sum
   double* v = dig2 + (bs ? DG : 0);                     // BSGS: key-switched part [2][lv+1][N]
@@ -391,10 +395,12 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
         z += p->nchunk;
         continue;
       }
-      // every giant step's inner sum down to Q at once, then rotated by j*bs and added
+      // every giant step's inner sum (its chunks added) down to Q at once, then
+      // rotated by j*bs and added
+      HIP_TRY(launch_sum_partials(L, a.part, p->chunks_per_giant, K, N, lp, acc, g));
       {
         KernelTimer kt(c, stream, PVFL_TIMING_MODDOWN, 8.0 * (double)g * (2 * KN + 2 * Q));
-        HIP_TRY(launch_moddown(L, a.part, 2 * g, lv, c->alpha, c->ks_dev + lv, ydown, cj));
+        HIP_TRY(launch_moddown(L, acc, 2 * g, lv, c->alpha, c->ks_dev + lv, ydown, cj));
         kt.stop();
       }
       HIP_TRY(launch_add_limbs(L, ob, cj, 2 * (lv + 1), N, qm, ob));
@@ -402,7 +408,7 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
         const double* cjj = cj + (size_t)j * 2 * Q;
         const int rot = j * bs;
         HIP_TRY(launch_modup(L, cjj, 0, 1, lv, c->ks_dev + lv, kl.n_tasks, yup, dig2, 0));
-        pvfl_status st = keyswitch_digits(c, keys, lv, dig2, rot, rot, acc, ydown, v, stream);
+        pvfl_status st = keyswitch_digits(c, keys, lv, dig2, rot, rot, acc, ydown, v, stream);  // acc reused: summed above
         if (st != PVFL_OK) return st;
         HIP_TRY(launch_automorph(L, cjj, lv + 1, N, rot, rct));
         HIP_TRY(launch_add_limbs(L, ob, rct, lv + 1, N, qm, ob));
@@ -541,4 +547,69 @@ extern "C" pvfl_status pvfl_matmul_ct_pt(const pvfl_plan* p, const void* ct_v, c
     }
   }
   return fail(PVFL_E_PLAN, "unknown plan kind");
+}
+
+// ---------------------------------------------------------------------------
+// Transposed diagonal conversion (Sec. 5.3, Eq. 7): [[A]] as Eq. 5 diagonals ->
+// [[A^T]] as Eq. 5 diagonals, e'_i = RotL(e_k, r) (see transpose_step)
+// ---------------------------------------------------------------------------
+namespace {
+// diagonal i of A^T is diagonal k of A rotated left by r slots
+void transpose_step(const pvfl_plan* p, int i, int* k, int* r) {
+  const int lo = p->info.mprime, mp = p->info.m_pad, np = p->info.n_pad, hi = std::max(mp, np);
+  *k = (lo - i) % lo;
+  if (mp >= np)
+    *r = i;
+  else
+    *r = i == 0 ? 0 : hi - lo + i;
+}
+
+pvfl_status transpose_check(const pvfl_plan* p) {
+  if (p->opts.kind != PVFL_PLAN_CTMAT) return fail(PVFL_E_PLAN, "the conversion takes a CTMAT plan");
+  const int width = std::max(p->info.m_pad, p->info.n_pad);
+  if ((int64_t)std::max(1, p->opts.pack) * width != p->ctx->N / 2)
+    return fail(PVFL_E_PLAN, "the conversion needs pack * max(m, n) = N/2 (every block holding the diagonal)");
+  return PVFL_OK;
+}
+}  // namespace
+
+extern "C" pvfl_status pvfl_ctmat_transpose_galois(const pvfl_plan* p, uint32_t* out, int32_t cap, int32_t* count) {
+  if (!p || !count || (!out && cap > 0)) return fail(PVFL_E_INVALID, "null argument");
+  pvfl_status st = transpose_check(p);
+  if (st != PVFL_OK) return st;
+  std::vector<uint32_t> g;
+  for (int i = 0; i < p->info.mprime; ++i) {
+    int k, r;
+    transpose_step(p, i, &k, &r);
+    if (r) g.push_back(galois_rotl(r, p->ctx->N));
+  }
+  std::sort(g.begin(), g.end());
+  g.erase(std::unique(g.begin(), g.end()), g.end());
+  *count = (int32_t)g.size();
+  if ((int32_t)g.size() > cap) return fail(PVFL_E_SHAPE, "buffer too small");
+  std::copy(g.begin(), g.end(), out);
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_ctmat_transpose(const pvfl_plan* p, const void* ct_in, const pvfl_rotkeys* keys,
+                                            void* ct_out, void* stream) {
+  if (!p || !ct_in || !ct_out) return fail(PVFL_E_INVALID, "null argument");
+  pvfl_status st = transpose_check(p);
+  if (st != PVFL_OK) return st;
+  if (ct_in == ct_out) return fail(PVFL_E_INVALID, "the conversion cannot run in place");
+  pvfl_ctx* c = p->ctx;
+  const size_t Q = (size_t)(p->lv + 1) * c->N;
+  for (int i = 0; i < p->info.mprime; ++i) {
+    int k, r;
+    transpose_step(p, i, &k, &r);
+    const double* src = (const double*)ct_in + (size_t)k * 2 * Q;
+    double* dst = (double*)ct_out + (size_t)i * 2 * Q;
+    if (r == 0) {
+      HIP_TRY(hipMemcpyAsync(dst, src, 2 * Q * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    } else {
+      if (!keys) return fail(PVFL_E_NOKEY, "the conversion needs rotation keys");
+      if ((st = pvfl_rotate(c, keys, p->lv, src, galois_rotl(r, c->N), 0, dst, stream)) != PVFL_OK) return st;
+    }
+  }
+  return PVFL_OK;
 }

@@ -1,9 +1,12 @@
-// Plan selection for the plaintext-matrix x ciphertext-vector product.
+// Plan selection for both operand forms of the product.
 //
-// For a shape (m, n) at a level the candidates are every valid combination of
-// plan kind (HYBRID, DIAG, ROW; Sec. 3-4), ModDown placement (lazy / per
-// rotation) and rotation schedule (all rotations hoisted, or a
-// baby-step/giant-step split with baby step b).  Two latency models rank them:
+// X (m x n) times an encrypted vector: every valid combination of plan kind
+// (HYBRID, DIAG, ROW; Sec. 3-4), ModDown placement (lazy / per rotation) and
+// rotation schedule (all rotations hoisted, or a baby-step/giant-step split
+// with baby step b).  [[A]] (m x n) times W (n x n_out): Alg. 3 with every
+// column-packing factor, or W^T times each encrypted row of A (a batch of m
+// HYBRID or DIAG products sharing one plaintext set).  Two latency models
+// rank them:
 //
 //  * analytic: the Table 2 operation counts of the plan (Mult, Add, Rot,
 //    HstRot) plus the ModUp / ModDown counts and the number of encoded
@@ -35,6 +38,7 @@ using namespace pvfl;
 namespace {
 constexpr int kFeatures = PVFL_PLAN_FEATURES;
 constexpr int kMaxCandidates = 64;
+constexpr int kMaxBatchDigits = 4;  // digits the batched fused kernel is instantiated for
 
 float lg1p(double x) { return (float)std::log2(1.0 + x); }
 
@@ -44,7 +48,7 @@ int ilog2i(int x) {
   return r;
 }
 
-void features_of(const pvfl_plan* p, float* f) {
+void features_of(const pvfl_plan* p, int batch, float* f) {
   const pvfl_plan_info& I = p->info;
   const pvfl_ctx* c = p->ctx;
   int k = 0;
@@ -59,10 +63,13 @@ void features_of(const pvfl_plan* p, float* f) {
   f[k++] = I.kind == PVFL_PLAN_HYBRID ? 1.f : 0.f;
   f[k++] = I.kind == PVFL_PLAN_DIAG ? 1.f : 0.f;
   f[k++] = I.kind == PVFL_PLAN_ROW ? 1.f : 0.f;
+  f[k++] = I.kind == PVFL_PLAN_CTMAT ? 1.f : 0.f;
   f[k++] = p->opts.lazy_moddown ? 1.f : 0.f;
   f[k++] = p->ras_rots.empty() ? 0.f : 1.f;
   f[k++] = I.bsgs ? 1.f : 0.f;
   f[k++] = I.bsgs ? (float)ilog2i(I.bsgs) : 0.f;
+  f[k++] = I.kind == PVFL_PLAN_CTMAT ? (float)ilog2i(std::max(1, p->opts.pack)) : 0.f;
+  f[k++] = (float)ilog2i(std::max(1, batch));
   f[k++] = lg1p((double)I.n_mult);
   f[k++] = lg1p((double)I.n_add);
   f[k++] = lg1p((double)I.n_rot);
@@ -75,8 +82,8 @@ void features_of(const pvfl_plan* p, float* f) {
   // k == kFeatures
 }
 
-// every valid option set for X (m x n) times an encrypted vector at `level`
-void enumerate(pvfl_ctx* c, int m, int n, int level, std::vector<pvfl_plan_opts>& out) {
+// every option set for X (m x n) times an encrypted vector at `level`
+void enumerate_vec(pvfl_ctx* c, int m, int n, int level, std::vector<pvfl_plan_opts>& out) {
   auto base = [&](int kind) {
     pvfl_plan_opts o{};
     o.kind = kind;
@@ -117,6 +124,35 @@ void enumerate(pvfl_ctx* c, int m, int n, int level, std::vector<pvfl_plan_opts>
   }
   out.push_back(base(PVFL_PLAN_ROW));
 }
+
+// [[A]] (m x n) times W (n x n_out): Alg. 3 with packing 1, 2, 4, ... as far as
+// it fits, and the per-row form (W^T, n_out x n, times each row of A)
+void enumerate_mat(pvfl_ctx* c, int m, int n, int n_out, int level, std::vector<pvfl_candidate>& out) {
+  const int S = c->N / 2;
+  const int width = std::max(1 << ilog2i(m), 1 << ilog2i(n));
+  for (int pack = 1; (int64_t)pack * width <= S; pack *= 2) {
+    pvfl_candidate k{};
+    k.opts.kind = PVFL_PLAN_CTMAT;
+    k.opts.m = m;
+    k.opts.n = n;
+    k.opts.n_out = n_out;
+    k.opts.level = level;
+    k.opts.pack = pack;
+    k.batch = 1;
+    out.push_back(k);
+  }
+  for (int kind : {PVFL_PLAN_HYBRID, PVFL_PLAN_DIAG}) {
+    pvfl_candidate k{};
+    k.opts.kind = kind;
+    k.opts.m = n_out;
+    k.opts.n = n;
+    k.opts.level = level;
+    k.opts.lazy_moddown = 1;
+    k.opts.pack = 1;
+    k.batch = m;
+    out.push_back(k);
+  }
+}
 }  // namespace
 
 struct pvfl_planner {
@@ -133,23 +169,34 @@ struct pvfl_planner {
 
 extern "C" int32_t pvfl_plan_num_features(void) { return kFeatures; }
 
-extern "C" pvfl_status pvfl_plan_features(const pvfl_plan* p, float* out, int32_t cap) {
+extern "C" pvfl_status pvfl_plan_features(const pvfl_plan* p, int32_t batch, float* out, int32_t cap) {
   if (!p || !out) return fail(PVFL_E_INVALID, "null argument");
   if (cap < kFeatures) return fail(PVFL_E_SHAPE, "feature buffer too small");
-  features_of(p, out);
+  if (batch < 1) return fail(PVFL_E_INVALID, "batch must be positive");
+  features_of(p, batch, out);
   return PVFL_OK;
 }
 
-extern "C" pvfl_status pvfl_plan_candidates(pvfl_ctx* c, int32_t m, int32_t n, int32_t level, pvfl_plan_opts* out,
-                                            int32_t cap, int32_t* count) {
+extern "C" pvfl_status pvfl_plan_candidates(pvfl_ctx* c, int32_t operand, int32_t m, int32_t n, int32_t n_out,
+                                            int32_t level, pvfl_candidate* out, int32_t cap, int32_t* count) {
   if (!c || !count || (!out && cap > 0)) return fail(PVFL_E_INVALID, "null argument");
   if (m < 1 || n < 1) return fail(PVFL_E_SHAPE, "m and n must be positive");
-  std::vector<pvfl_plan_opts> all, ok;
-  enumerate(c, m, n, level, all);
-  for (const pvfl_plan_opts& o : all) {
+  std::vector<pvfl_candidate> all, ok;
+  if (operand == PVFL_OPERAND_CT_VEC) {
+    std::vector<pvfl_plan_opts> v;
+    enumerate_vec(c, m, n, level, v);
+    for (const pvfl_plan_opts& o : v) all.push_back(pvfl_candidate{o, 1});
+  } else if (operand == PVFL_OPERAND_CT_MAT) {
+    if (n_out < 1) return fail(PVFL_E_SHAPE, "n_out must be positive");
+    enumerate_mat(c, m, n, n_out, level, all);
+  } else {
+    return fail(PVFL_E_INVALID, "unknown operand form");
+  }
+  for (const pvfl_candidate& k : all) {
     pvfl_plan* p = nullptr;
-    if (pvfl_plan_create(c, &o, &p) == PVFL_OK) {
-      ok.push_back(o);
+    if (pvfl_plan_create(c, &k.opts, &p) == PVFL_OK) {
+      // the per-row form runs as one batch, whose fused kernel takes up to 4 digits
+      if (k.batch == 1 || p->beta <= kMaxBatchDigits) ok.push_back(k);
       pvfl_plan_destroy(p);
     }
   }
@@ -159,11 +206,13 @@ extern "C" pvfl_status pvfl_plan_candidates(pvfl_ctx* c, int32_t m, int32_t n, i
   return PVFL_OK;
 }
 
-extern "C" pvfl_status pvfl_plan_analytic_ms(const pvfl_plan* p, const double* costs, double* ms) {
+extern "C" pvfl_status pvfl_plan_analytic_ms(const pvfl_plan* p, int32_t batch, const double* costs, double* ms) {
   if (!p || !costs || !ms) return fail(PVFL_E_INVALID, "null argument");
+  if (batch < 1) return fail(PVFL_E_INVALID, "batch must be positive");
   const pvfl_plan_info& I = p->info;
-  const double counts[PVFL_COST_TERMS] = {(double)I.n_mult,   (double)I.n_add,     (double)I.n_rot,
-                                          (double)I.n_hstrot, (double)I.n_modup,   (double)I.n_moddown,
+  const double B = (double)batch;
+  const double counts[PVFL_COST_TERMS] = {B * I.n_mult,   B * I.n_add,     B * I.n_rot,
+                                          B * I.n_hstrot, B * I.n_modup,   B * I.n_moddown,
                                           (double)I.n_pts * I.pt_limbs, 1.0};
   double t = 0;
   for (int i = 0; i < PVFL_COST_TERMS; ++i) t += counts[i] * costs[i];
@@ -194,23 +243,23 @@ extern "C" pvfl_status pvfl_planner_create(pvfl_mlp* mlp, const float* x_mean, c
 
 extern "C" void pvfl_planner_destroy(pvfl_planner* pl) { delete pl; }
 
-extern "C" pvfl_status pvfl_plan_choose(pvfl_planner* pl, pvfl_ctx* c, int32_t m, int32_t n, int32_t level,
-                                        const double* costs, pvfl_plan_opts* chosen, double* predicted_ms,
-                                        void* stream) {
+extern "C" pvfl_status pvfl_plan_choose(pvfl_planner* pl, pvfl_ctx* c, int32_t operand, int32_t m, int32_t n,
+                                        int32_t n_out, int32_t level, const double* costs, pvfl_candidate* chosen,
+                                        double* predicted_ms, void* stream) {
   if (!c || !chosen) return fail(PVFL_E_INVALID, "null argument");
   if (!costs && (!pl || !pl->mlp)) return fail(PVFL_E_INVALID, "neither a network nor operation costs given");
-  std::vector<pvfl_plan_opts> cand(kMaxCandidates);
+  std::vector<pvfl_candidate> cand(kMaxCandidates);
   int32_t nc = 0;
-  pvfl_status st = pvfl_plan_candidates(c, m, n, level, cand.data(), kMaxCandidates, &nc);
+  pvfl_status st = pvfl_plan_candidates(c, operand, m, n, n_out, level, cand.data(), kMaxCandidates, &nc);
   if (st != PVFL_OK) return st;
   if (nc == 0) return fail(PVFL_E_PLAN, "no valid plan for this shape");
   std::vector<float> x((size_t)nc * kFeatures);
   std::vector<double> pred(nc);
   for (int i = 0; i < nc; ++i) {
     pvfl_plan* p = nullptr;
-    if ((st = pvfl_plan_create(c, &cand[i], &p)) != PVFL_OK) return st;
-    features_of(p, &x[(size_t)i * kFeatures]);
-    if (costs) pvfl_plan_analytic_ms(p, costs, &pred[i]);
+    if ((st = pvfl_plan_create(c, &cand[i].opts, &p)) != PVFL_OK) return st;
+    features_of(p, cand[i].batch, &x[(size_t)i * kFeatures]);
+    if (costs) pvfl_plan_analytic_ms(p, cand[i].batch, costs, &pred[i]);
     pvfl_plan_destroy(p);
   }
   if (!costs) {

@@ -1,26 +1,33 @@
 """Plan selection: measured latencies, the two latency models, and regret.
 
-    python -m paper_2405_00482_amd.planner collect --configs C1 C2 C3 C4 --shapes 64 --out DB.json
-        times every candidate plan (encode of X plus the encrypted product,
-        per call, on the current GPU) for seeded shapes of each parameter set
-        and writes the records (shape, options, features, operation counts,
-        milliseconds) -- the exhaustive tuning the planner is judged against.
+    python -m paper_2405_00482_amd.planner collect --out DB.json
+        times every candidate plan on the current GPU for seeded shapes of
+        each parameter set and writes the records (operand form, shape,
+        options, batch, features, operation counts, milliseconds) -- the
+        exhaustive tuning the planner is judged against.
+          * X (m x n) times an encrypted vector: encode of X plus the product,
+            per call (C1-C4 and C4's digit-count variants).
+          * [[A]] (m x n) times W (n x n_out): Alg. 3 (encode W's packed
+            columns plus the product) or the per-row form (encode W^T once,
+            then the batched product over the m encrypted rows).
     python -m paper_2405_00482_amd.planner evaluate DB.json
         trains the latency network on the training shapes (GPU kernels),
         fits the analytic model, and prints the regret of each on the
         held-out shapes.
 
 Regret of a choice = its measured latency / the best measured latency of
-that shape - 1.  Every computation on the plans runs in libpvfl; this module
-only moves data, fits the analytic model's per-operation costs (non-negative
-least squares over the training records) and drives the network's training
-kernels.
+that shape - 1.  Shapes of C4 and its variants C4a1, C4a2 (one and two
+special primes: six and three key-switch digits instead of two) are the
+same seeded shapes, so their candidates are pooled: the choice includes the
+digit count.  Every computation on the plans runs in libpvfl; this module
+only moves data, fits the analytic model's per-operation costs
+(non-negative least squares over the training records) and drives the
+network's training kernels.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -33,32 +40,50 @@ from . import workloads as W
 DEFAULT_DB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned", "plan_latency_mi355x.json")
 
 FEATURE_NAMES = ("log2_N", "limbs", "alpha", "beta", "K", "log2_m", "log2_n", "log2_mprime", "hybrid", "diag", "row",
-                 "lazy", "ras_in_ct", "bsgs", "log2_bsgs", "lg_mult", "lg_add", "lg_rot", "lg_hstrot", "lg_modup",
-                 "lg_moddown", "lg_pt_limbs", "lg_keys", "lg_blocks")
+                 "ctmat", "lazy", "ras_in_ct", "bsgs", "log2_bsgs", "log2_pack", "log2_batch", "lg_mult", "lg_add",
+                 "lg_rot", "lg_hstrot", "lg_modup", "lg_moddown", "lg_pt_limbs", "lg_keys", "lg_blocks")
 assert len(FEATURE_NAMES) == pvfl.PLAN_FEATURES
 
+VEC_CONFIGS = ["C1", "C2", "C3", "C4", "C4a1", "C4a2"]
+MAT_CONFIGS = ["C4", "C4a1", "C4a2"]
 
-def counts_of(info: dict) -> list:
+
+def family(config: str) -> str:
+    """digit-count variants of one parameter set share shapes (and a choice)"""
+    return config[:2]
+
+
+def counts_of(info: dict, batch: int = 1) -> list:
     """the analytic model's count vector (pvfl_plan_analytic_ms order)"""
-    return [info["n_mult"], info["n_add"], info["n_rot"], info["n_hstrot"], info["n_modup"], info["n_moddown"],
-            info["n_pts"] * info["pt_limbs"], 1]
+    b = batch
+    return [b * info["n_mult"], b * info["n_add"], b * info["n_rot"], b * info["n_hstrot"], b * info["n_modup"],
+            b * info["n_moddown"], info["n_pts"] * info["pt_limbs"], 1]
 
 
 def is_test_shape(idx: int) -> bool:
     return idx % 4 == 3
 
 
+def mat_shapes(name: str, count: int):
+    """[[A]] (m x n) times W (n x n_out) shapes of VFL layers: m (batch) ~
+    logU[16, 1024], n (inputs) and n_out (outputs) ~ logU[8, 512]"""
+    g = W.rng(name, 11)
+    m = np.exp(g.uniform(np.log(16), np.log(1024), size=count)).astype(np.int64)
+    n = np.exp(g.uniform(np.log(8), np.log(512), size=count)).astype(np.int64)
+    k = np.exp(g.uniform(np.log(8), np.log(512), size=count)).astype(np.int64)
+    return [(int(a), int(b), int(c)) for a, b, c in zip(m, n, k)]
+
+
 # ---------------------------------------------------------------------------
 # exhaustive timing
 # ---------------------------------------------------------------------------
-def _time_plan(plan, X, ct, pt, out, ws, keys, torch, budget_ms: float = 60.0) -> float:
+def _timed(fn, torch, budget_ms: float = 60.0) -> float:
     s = torch.cuda.current_stream()
 
     def once():
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
-        plan.encode_pt(X, pt)
-        plan.matmul(ct, pt, keys, out, ws)
+        fn()
         e1.record(s)
         e1.synchronize()
         return e0.elapsed_time(e1)
@@ -70,7 +95,16 @@ def _time_plan(plan, X, ct, pt, out, ws, keys, torch, budget_ms: float = 60.0) -
     return float(np.median([once() for _ in range(reps)]))
 
 
-def collect(names, count: int, log=print) -> list:
+def _record(operand, name, idx, shape, cand, plan, ms):
+    b = cand.get("batch", 1)
+    opts = {k: v for k, v in cand.items() if k != "batch"}
+    return {"operand": operand, "config": name, "idx": idx, "m": shape[0], "n": shape[1],
+            "n_out": shape[2] if len(shape) > 2 else 0, "opts": opts, "batch": b,
+            "features": [round(x, 5) for x in plan.features(b)], "counts": counts_of(plan.info, b),
+            "ms": round(float(ms), 5)}
+
+
+def collect_vec(names, count: int, log=print) -> list:
     import torch
     recs = []
     for name in names:
@@ -97,10 +131,12 @@ def collect(names, count: int, log=print) -> list:
                 out = torch.empty(p.bytes("ct_out") // 8, **f64)
                 ws = torch.empty(max(1, p.bytes("workspace") // 8), **f64)
                 p.encrypt(sk, y, 5 + idx, ct)
-                ms = _time_plan(p, X, ct, pt, out, ws, keys, torch)
-                rec = {"config": name, "idx": idx, "m": m, "n": n, "opts": o, "features": p.features(),
-                       "counts": counts_of(p.info), "ms": ms}
-                recs.append(rec)
+
+                def run():
+                    p.encode_pt(X, pt)
+                    p.matmul(ct, pt, keys, out, ws)
+                ms = _timed(run, torch)
+                recs.append(_record(0, name, idx, (m, n), o, p, ms))
                 row.append(ms)
                 del pt, ct, out, ws
             best = int(np.argmin(row))
@@ -111,14 +147,81 @@ def collect(names, count: int, log=print) -> list:
     return recs
 
 
+def collect_mat(names, count: int, log=print) -> list:
+    import torch
+    recs = []
+    for name in names:
+        ctx = pvfl.Context.from_dict(W.params_dict(name))
+        sd = W.seeds(name)
+        sk = ctx.keygen(sd["sk"])
+        shapes = mat_shapes(name, count)
+        cands = [ctx.candidates(m, n, operand=pvfl.OPERAND_CT_MAT, n_out=k) for (m, n, k) in shapes]
+        plans = [[ctx.plan_from(o) for o in cs] for cs in cands]
+        gal = sorted(set(g for ps in plans for p in ps for g in p.galois()))
+        keys = ctx.rotkeys(sk, gal, sd["rotkeys"]) if gal else None
+        torch.cuda.synchronize()
+        log(f"[planner] {name} [[A]]W: {len(shapes)} shapes, {sum(len(c) for c in cands)} candidates, "
+            f"{len(gal)} rotation keys")
+        f64 = dict(dtype=torch.float64, device="cuda")
+        for idx, ((m, n, k), cs, ps) in enumerate(zip(shapes, cands, plans)):
+            g = W.rng(name, 2000 + idx)
+            A = torch.from_numpy(g.uniform(-1, 1, (m, n))).cuda()
+            Wm = torch.from_numpy(g.standard_normal((n, k)) * 0.1).cuda()
+            WT = Wm.t().contiguous()
+            row = []
+            for o, p in zip(cs, ps):
+                if o["kind"] == pvfl.PLAN_CTMAT:
+                    # Alg. 3: [[A]] sent as its diagonals (encryption is the key owner's, untimed)
+                    pt = torch.empty(p.bytes("pt") // 8, **f64)
+                    ct = torch.empty(p.bytes("ct_in") // 8, **f64)
+                    out = torch.empty(p.bytes("ct_out") // 8, **f64)
+                    p.encrypt(sk, A, 7 + idx, ct)
+
+                    def run():
+                        p.encode_pt(Wm, pt)
+                        p.matmul(ct, pt, None, out)
+                    ms = _timed(run, torch)
+                    del pt, ct, out
+                else:
+                    # per-row form: W^T (k x n) times each encrypted row of A, one shared plaintext set
+                    pt = torch.empty(p.bytes("pt") // 8, **f64)
+                    cts = [torch.empty(p.bytes("ct_in") // 8, **f64) for _ in range(m)]
+                    outs = [torch.empty(p.bytes("ct_out") // 8, **f64) for _ in range(m)]
+                    rows = [A[r].contiguous() for r in range(m)]
+                    b = pvfl.Batch(ctx, [p] * m, v=rows, pt=[pt] * m, ct=cts, out=outs, keys=keys)
+                    b.encrypt(sk, 7 + idx)
+
+                    def run():
+                        p.encode_pt(WT, pt)
+                        b.matmul()
+                    ms = _timed(run, torch)
+                    del b, pt, cts, outs, rows
+                recs.append(_record(1, name, idx, (m, n, k), o, p, ms))
+                row.append(ms)
+            best = int(np.argmin(row))
+            log(f"[planner] {name} [[A]]W #{idx} {m}x{n}x{k}: {len(cs)} candidates, best {row[best]:.3f} ms "
+                f"({describe(cs[best])})")
+        del keys, plans
+        torch.cuda.empty_cache()
+    return recs
+
+
 def describe(o: dict) -> str:
     kind = {0: "HYBRID", 1: "DIAG", 2: "ROW", 3: "CTMAT"}[o["kind"]]
+    if o["kind"] == 3:
+        return f"CTMAT pack{o.get('pack', 1)}"
     s = kind + ("" if o["kind"] == 2 else (" lazy" if o["lazy_moddown"] else " eager"))
     if o.get("bsgs"):
         s += f" bsgs{o['bsgs']}"
     if o.get("ras_in_ct"):
         s += " ras-in-ct"
+    if o.get("batch", 1) > 1:
+        s += f" per-row x{o['batch']}"
     return s
+
+
+def describe_rec(r: dict) -> str:
+    return f"{r['config']} " + describe({**r["opts"], "batch": r.get("batch", 1)})
 
 
 # ---------------------------------------------------------------------------
@@ -188,43 +291,65 @@ def analytic_predict_ms(costs, recs) -> np.ndarray:
     return np.array([float(np.dot(r["counts"], costs[r["config"]])) for r in recs])
 
 
+def shape_key(r) -> tuple:
+    return (r.get("operand", 0), family(r["config"]), r["idx"])
+
+
 def regrets(recs, pred) -> dict:
-    """per shape: measured latency of the predicted-best candidate over the
-    measured best, minus one"""
+    """per shape (candidates of a parameter set's digit-count variants pooled):
+    measured latency of the predicted-best candidate over the measured best,
+    minus one"""
     by = {}
     for r, p in zip(recs, pred):
-        by.setdefault((r["config"], r["idx"]), []).append((p, r["ms"], r))
+        by.setdefault(shape_key(r), []).append((p, r["ms"], r))
     out = []
     for key, rows in sorted(by.items()):
         best = min(ms for _, ms, _ in rows)
         pick = min(rows, key=lambda t: t[0])
-        out.append({"config": key[0], "idx": key[1], "regret": pick[1] / best - 1.0,
-                    "chosen": describe(pick[2]["opts"]), "best": describe(min(rows, key=lambda t: t[1])[2]["opts"])})
+        out.append({"operand": key[0], "config": key[1], "idx": key[2], "regret": pick[1] / best - 1.0,
+                    "chosen": describe_rec(pick[2]), "best": describe_rec(min(rows, key=lambda t: t[1])[2])})
     rg = np.array([o["regret"] for o in out])
     return {"mean": float(rg.mean()), "max": float(rg.max()), "geo": float(np.exp(np.mean(np.log1p(rg)))) - 1.0,
             "shapes": out}
 
 
 def fixed_choice_regret(recs, pick) -> dict:
-    """regret of always taking the candidate for which pick(opts) is True"""
-    pred = np.array([0.0 if pick(r["opts"]) else 1.0 for r in recs])
+    """regret of always taking the candidate for which pick(record) is True
+    (shapes where no candidate qualifies take their first)"""
+    pred = np.array([0.0 if pick(r) else 1.0 for r in recs])
     return regrets(recs, pred)
+
+
+def paper_default(r) -> bool:
+    """the paper's choices: the hybrid with hoisted rotations for X [[y]]
+    (Sec. 4) and Alg. 3 for [[A]] W (Sec. 5), on the configured digit count"""
+    o = r["opts"]
+    if r["config"] not in ("C1", "C2", "C3", "C4"):
+        return False
+    if r.get("operand", 0) == 1:
+        return o["kind"] == 3 and o.get("pack", 1) == 1
+    return o["kind"] == 0 and o["lazy_moddown"] and not o.get("bsgs", 0)
 
 
 def evaluate(recs, log=print, steps: int = 4000) -> dict:
     train, test = split(recs)
     costs = fit_analytic(train)
     net, st = train_mlp(train, steps=steps, log=log)
-    res = {
-        "mlp": regrets(test, mlp_predict_ms(net, st, test)),
-        "analytic": regrets(test, analytic_predict_ms(costs, test)),
-        "paper_default": fixed_choice_regret(test, lambda o: o["kind"] == 0 and o["lazy_moddown"] and not o["bsgs"]),
-        "costs": costs,
-        "n_train": len(train), "n_test": len(test),
-    }
-    for k in ("mlp", "analytic", "paper_default"):
-        log(f"[planner] {k:14s} regret on {len(res[k]['shapes'])} held-out shapes: mean {res[k]['mean']:.4f}, "
-            f"max {res[k]['max']:.4f}")
+    pm = mlp_predict_ms(net, st, test)
+    pa = analytic_predict_ms(costs, test)
+    res = {"costs": costs, "n_train": len(train), "n_test": len(test)}
+    for operand, label in ((None, "all"), (0, "X[[y]]"), (1, "[[A]]W")):
+        sel = [i for i, r in enumerate(test) if operand is None or r.get("operand", 0) == operand]
+        if not sel:
+            continue
+        sub = [test[i] for i in sel]
+        res[label] = {"mlp": regrets(sub, pm[sel]), "analytic": regrets(sub, pa[sel]),
+                      "paper_default": fixed_choice_regret(sub, paper_default)}
+        for k in ("mlp", "analytic", "paper_default"):
+            v = res[label][k]
+            log(f"[planner] {label:7s} {k:14s} regret on {len(v['shapes'])} held-out shapes: mean {v['mean']:.4f}, "
+                f"max {v['max']:.4f}")
+    res["mlp"], res["analytic"], res["paper_default"] = (res["all"][k] for k in ("mlp", "analytic", "paper_default"))
     return res, net, st
 
 
@@ -232,8 +357,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     c = sub.add_parser("collect")
-    c.add_argument("--configs", nargs="+", default=["C1", "C2", "C3", "C4"])
+    c.add_argument("--vec-configs", nargs="*", default=VEC_CONFIGS)
+    c.add_argument("--mat-configs", nargs="*", default=MAT_CONFIGS)
     c.add_argument("--shapes", type=int, default=64)
+    c.add_argument("--mat-shapes", type=int, default=48)
     c.add_argument("--out", default=DEFAULT_DB)
     e = sub.add_parser("evaluate")
     e.add_argument("db", nargs="?", default=DEFAULT_DB)
@@ -241,10 +368,12 @@ def main(argv=None):
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
     if a.cmd == "collect":
-        recs = collect(a.configs, a.shapes, log=log)
+        recs = collect_vec(a.vec_configs, a.shapes, log=log) + collect_mat(a.mat_configs, a.mat_shapes, log=log)
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
         with open(a.out, "w") as f:
-            json.dump({"device": "MI355X", "what": "ms of encode_pt + matmul per call, median", "records": recs}, f)
+            json.dump({"device": "MI355X", "what": "ms per call of every candidate plan (median of repeats)",
+                       "command": "python -m paper_2405_00482_amd.planner collect", "records": recs}, f,
+                      separators=(",", ":"))
         log(f"[planner] wrote {len(recs)} records to {a.out}")
     else:
         with open(a.db) as f:

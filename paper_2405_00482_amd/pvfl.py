@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("log2_scale", ctypes.c_double)]
 
 
-PLAN_FEATURES = 24
+PLAN_FEATURES = 27
+OPERAND_CT_VEC, OPERAND_CT_MAT = 0, 1
 COST_TERMS = 8
 COST_NAMES = ("mult", "add", "rot", "hstrot", "modup", "moddown", "pt_limbs", "const")
 
@@ -44,6 +45,10 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("n_out", ctypes.c_int32),
                 ("level", ctypes.c_int32), ("lazy_moddown", ctypes.c_int32), ("ras_in_ct", ctypes.c_int32),
                 ("pack", ctypes.c_int32), ("pt_log2_scale", ctypes.c_double), ("bsgs", ctypes.c_int32)]
+
+
+class Candidate(ctypes.Structure):
+    _fields_ = [("opts", PlanOpts), ("batch", ctypes.c_int32)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -102,13 +107,15 @@ def lib():
             "pvfl_decrypt_decode": [_VP, _VP, _VP, _VP, _VP],
             "pvfl_timing_enable": [_VP, i32],
             "pvfl_mlp_create": [i32, i32, i32, u64, ctypes.POINTER(_VP)],
-            "pvfl_plan_candidates": [_VP, i32, i32, i32, ctypes.POINTER(PlanOpts), i32, ctypes.POINTER(i32)],
-            "pvfl_plan_features": [_VP, ctypes.POINTER(ctypes.c_float), i32],
-            "pvfl_plan_analytic_ms": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+            "pvfl_ctmat_transpose_galois": [_VP, ctypes.POINTER(u32), i32, ctypes.POINTER(i32)],
+            "pvfl_ctmat_transpose": [_VP, _VP, _VP, _VP, _VP],
+            "pvfl_plan_candidates": [_VP, i32, i32, i32, i32, i32, ctypes.POINTER(Candidate), i32, ctypes.POINTER(i32)],
+            "pvfl_plan_features": [_VP, i32, ctypes.POINTER(ctypes.c_float), i32],
+            "pvfl_plan_analytic_ms": [_VP, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
             "pvfl_planner_create": [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                     ctypes.c_float, ctypes.c_float, ctypes.POINTER(_VP)],
-            "pvfl_plan_choose": [_VP, _VP, i32, i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PlanOpts),
-                                 ctypes.POINTER(ctypes.c_double), _VP],
+            "pvfl_plan_choose": [_VP, _VP, i32, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(Candidate), ctypes.POINTER(ctypes.c_double), _VP],
             "pvfl_mlp_get_params": [_VP, _VP, _VP],
             "pvfl_mlp_set_params": [_VP, _VP, _VP],
             "pvfl_mlp_forward": [_VP, _VP, i32, _VP, _VP],
@@ -219,13 +226,13 @@ class Context(_Handle):
         _check(lib().pvfl_rotkeys_gen(self.h, sk.h, arr, len(g), seed, ctypes.byref(h)))
         return RotKeys(h, list(g), keep=(self,))
 
-    def candidates(self, m: int, n: int, level: int = -1) -> list:
-        """every valid plan option set for X (m x n) times an encrypted vector"""
+    def candidates(self, m: int, n: int, level: int = -1, operand: int = 0, n_out: int = 0) -> list:
+        """every valid candidate: option dict plus "batch" (products it runs)"""
         cap = 64
-        arr = (PlanOpts * cap)()
+        arr = (Candidate * cap)()
         cnt = ctypes.c_int32()
-        _check(lib().pvfl_plan_candidates(self.h, m, n, level, arr, cap, ctypes.byref(cnt)))
-        return [opts_dict(arr[i]) for i in range(cnt.value)]
+        _check(lib().pvfl_plan_candidates(self.h, operand, m, n, n_out, level, arr, cap, ctypes.byref(cnt)))
+        return [cand_dict(arr[i]) for i in range(cnt.value)]
 
     def plan_from(self, o: dict) -> "Plan":
         return self.plan(o["kind"], o["m"], o["n"], n_out=o.get("n_out", 0), level=o.get("level", -1),
@@ -323,15 +330,28 @@ class Plan(_Handle):
     def decrypt_decode(self, sk, ct, out):
         _check(lib().pvfl_decrypt_decode(self.h, sk.h, _ptr(ct), _ptr(out), _stream()))
 
-    def features(self) -> list:
+    def transpose_galois(self) -> list:
+        """Galois elements the transposed diagonal conversion (Eq. 7) needs"""
+        cap = 8192
+        arr = (ctypes.c_uint32 * cap)()
+        cnt = ctypes.c_int32()
+        _check(lib().pvfl_ctmat_transpose_galois(self.h, arr, cap, ctypes.byref(cnt)))
+        return [int(arr[i]) for i in range(cnt.value)]
+
+    def transpose(self, ct_in, keys, ct_out):
+        """[[A]] diagonals -> [[A^T]] diagonals (Eq. 7)"""
+        _check(lib().pvfl_ctmat_transpose(self.h, _ptr(ct_in), keys.h if keys is not None else None, _ptr(ct_out),
+                                          _stream()))
+
+    def features(self, batch: int = 1) -> list:
         arr = (ctypes.c_float * PLAN_FEATURES)()
-        _check(lib().pvfl_plan_features(self.h, arr, PLAN_FEATURES))
+        _check(lib().pvfl_plan_features(self.h, batch, arr, PLAN_FEATURES))
         return [float(x) for x in arr]
 
-    def analytic_ms(self, costs) -> float:
+    def analytic_ms(self, costs, batch: int = 1) -> float:
         c = (ctypes.c_double * COST_TERMS)(*costs)
         out = ctypes.c_double()
-        _check(lib().pvfl_plan_analytic_ms(self.h, c, ctypes.byref(out)))
+        _check(lib().pvfl_plan_analytic_ms(self.h, batch, c, ctypes.byref(out)))
         return out.value
 
     def matmul(self, ct, pt, keys, out, ws=None):
@@ -340,17 +360,24 @@ class Plan(_Handle):
                                        _ptr(ws), ws_bytes, _stream()))
 
 
-def choose_analytic(ctx: Context, m: int, n: int, costs, level: int = -1):
+def choose_analytic(ctx: Context, m: int, n: int, costs, level: int = -1, operand: int = 0, n_out: int = 0):
     """the candidate of least analytic latency (no network needed)"""
     c = (ctypes.c_double * COST_TERMS)(*costs)
-    o = PlanOpts()
+    k = Candidate()
     pred = ctypes.c_double()
-    _check(lib().pvfl_plan_choose(None, ctx.h, m, n, level, c, ctypes.byref(o), ctypes.byref(pred), _stream()))
-    return opts_dict(o), pred.value
+    _check(lib().pvfl_plan_choose(None, ctx.h, operand, m, n, n_out, level, c, ctypes.byref(k), ctypes.byref(pred),
+                                  _stream()))
+    return cand_dict(k), pred.value
 
 
 def opts_dict(o: PlanOpts) -> dict:
     return {name: getattr(o, name) for name, _ in o._fields_}
+
+
+def cand_dict(k: Candidate) -> dict:
+    d = opts_dict(k.opts)
+    d["batch"] = int(k.batch)
+    return d
 
 
 class Planner(_Handle):
@@ -365,12 +392,13 @@ class Planner(_Handle):
         _check(lib().pvfl_planner_create(mlp.h if mlp is not None else None, xm, xs, y_mean, y_std, ctypes.byref(h)))
         super().__init__(h, keep=(mlp,))
 
-    def choose(self, ctx: Context, m: int, n: int, level: int = -1, costs=None):
+    def choose(self, ctx: Context, m: int, n: int, level: int = -1, costs=None, operand: int = 0, n_out: int = 0):
         c = (ctypes.c_double * COST_TERMS)(*costs) if costs is not None else None
-        o = PlanOpts()
+        k = Candidate()
         pred = ctypes.c_double()
-        _check(lib().pvfl_plan_choose(self.h, ctx.h, m, n, level, c, ctypes.byref(o), ctypes.byref(pred), _stream()))
-        return opts_dict(o), pred.value
+        _check(lib().pvfl_plan_choose(self.h, ctx.h, operand, m, n, n_out, level, c, ctypes.byref(k),
+                                      ctypes.byref(pred), _stream()))
+        return cand_dict(k), pred.value
 
 
 def _ptr_array(items):

@@ -32,7 +32,13 @@ def params_dict(name: str) -> dict:
 
 
 def seed_of(name: str) -> int:
-    return 1000 + int(name[1:])
+    """1000 + the configuration's index (C4a1, C4a2: C4's digit-count variants, seeded as C4)"""
+    digits = ""
+    for ch in name[1:]:
+        if not ch.isdigit():
+            break
+        digits += ch
+    return 1000 + int(digits)
 
 
 def rng(name: str, salt: int = 0) -> np.random.Generator:

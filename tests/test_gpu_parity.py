@@ -326,3 +326,45 @@ def test_row_plan_bit_exact():
     assert_same(got[1], want.c1, "row c1")
     z = O.decrypt_decode(prm, s, want, prm.scale ** 2 / prm.q[lv])
     assert np.linalg.norm(z[:m] - X @ y) / np.linalg.norm(X @ y) < 2 ** -20
+
+
+@pytest.mark.parametrize("m,n", [(16, 4), (4, 16), (8, 8)])
+def test_transposed_conversion_bit_exact(m, n):
+    """Eq. 7 (reading): the GPU's [[A^T]] diagonals equal the oracle's residue for residue"""
+    prm = O.Params.from_dict(W.params_dict("C1"))
+    ctx = context("C1")
+    N, S, lv = prm.N, prm.slots, prm.L
+    width = max(PL.pow2_ceil(m), PL.pow2_ceil(n))
+    rng = np.random.default_rng(m * 3 + n)
+    A = rng.uniform(-1, 1, (m, n))
+    oplan = PL.CtMatPlan(m, n, 1, S, pack=S // width)
+    plan = ctx.plan(pvfl.PLAN_CTMAT, m, n, n_out=1, pack=S // width)
+    gal = plan.transpose_galois()
+    assert gal == PL.transpose_galois(oplan, N)
+    sk_gpu = ctx.keygen(SEED_SK)
+    s = O.keygen(prm, SEED_SK)
+    keys = ctx.rotkeys(sk_gpu, gal, SEED_KEYS) if gal else None
+    okeys = {g: O.rotkey_gen(prm, s, g, SEED_KEYS) for g in gal}
+    ct = dev_f64(plan.bytes("ct_in") // 8)
+    octs = []
+    Q2 = 2 * (lv + 1) * N
+    for i in range(oplan.ndiag):
+        mi = O.encode(PL.ctmat_ct_slots(oplan, A, i), N, prm.scale)
+        one = dev_f64(Q2)
+        ctx.encrypt_coeffs(sk_gpu, lv, dev_i64(mi), SEED_ENC + i, one)
+        ct[i * Q2:(i + 1) * Q2] = one
+        octs.append(O.encrypt(prm, s, mi, lv, SEED_ENC + i))
+    out = dev_f64(plan.bytes("ct_in") // 8)
+    plan.transpose(ct, keys, out)
+    got = export_ct(ctx, lv, out, oplan.ndiag)
+    want = PL.ctmat_transpose(prm, oplan, octs, okeys)
+    for i, w in enumerate(want):
+        assert_same(got[i, 0], w.c0, f"diag {i} c0")
+        assert_same(got[i, 1], w.c1, f"diag {i} c1")
+
+
+def test_transposed_conversion_rejects_partial_packing():
+    ctx = context("C1")
+    plan = ctx.plan(pvfl.PLAN_CTMAT, 16, 4, n_out=1, pack=1)
+    with pytest.raises(pvfl.PvflError):
+        plan.transpose_galois()

@@ -8,6 +8,7 @@ import pytest
 
 from oracle import oracle as O
 from oracle import plans as PL
+from paper_2405_00482_amd import pvfl
 from paper_2405_00482_amd import workloads as W
 
 from gpu_util import context, dev_f64, export, export_ct, torch
@@ -196,3 +197,36 @@ def test_ring_2_15_full_size_product():
     assert err < 2.0 ** -20
     del keys
     t.cuda.empty_cache()
+
+
+def test_vfl_nn_backward_via_transposed_conversion():
+    """VFL-NN layer at C4 (Sec. 5.3): [[H]] (256 x 64) sent once as Eq. 5
+    diagonals; forward [[H]] W by Alg. 3, backward H^T delta^T by converting
+    [[H]] to [[H^T]] (Eq. 7) and Alg. 3 again.  Both within 2^-20."""
+    ctx = context("C4")
+    H, Wm, _ = W.c4_inputs()
+    rng = np.random.default_rng(44)
+    D = rng.uniform(-1, 1, (H.shape[0], 32))          # delta_act^T: batch x n'
+    m, n = H.shape
+    width = max(m, n)
+    pack = (ctx.N // 2) // width
+    fwd = ctx.plan(pvfl.PLAN_CTMAT, m, n, n_out=Wm.shape[1], pack=pack)
+    bwd = ctx.plan(pvfl.PLAN_CTMAT, n, m, n_out=D.shape[1], pack=pack)
+    sk = ctx.keygen(9)
+    keys = ctx.rotkeys(sk, fwd.transpose_galois(), 10)
+    ct = dev_f64(fwd.bytes("ct_in") // 8)
+    fwd.encrypt(sk, to_dev(H), 11, ct)
+    for plan, B, ct_in, ref in ((fwd, Wm, ct, H @ Wm), (bwd, D, None, H.T @ D)):
+        if ct_in is None:
+            ct_in = dev_f64(bwd.bytes("ct_in") // 8)
+            fwd.transpose(ct, keys, ct_in)
+        pt = dev_f64(plan.bytes("pt") // 8)
+        out = dev_f64(plan.bytes("ct_out") // 8)
+        y = dev_f64(ref.size)
+        plan.encode_pt(to_dev(B), pt)
+        plan.matmul(ct_in, pt, None, out)
+        plan.decrypt_decode(sk, out, y)
+        got = y.cpu().numpy().reshape(ref.shape)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"{'forward' if plan is fwd else 'backward'}: rel err 2^{np.log2(err):.2f}")
+        assert err < 2.0 ** -20

@@ -159,3 +159,54 @@ def test_bsgs_encrypted(m, n, bs):
     outs = PL.hybrid_matmul_bsgs(prm, plan, cts, pts, keys, bs)
     zs = [O.decrypt_decode(prm, s, ct, prm.scale * prm.scale) for ct in outs]
     assert rel_err(PL.hybrid_lazy_ras(plan, zs), X @ y) < 1e-3
+
+
+@pytest.mark.parametrize("m,n", [(4, 4), (8, 2), (2, 8), (16, 4), (4, 16), (3, 5), (7, 3), (64, 16), (1, 8)])
+def test_transpose_conversion_is_a_slot_permutation(m, n):
+    """Eq. 7 (reading): rotating A's diagonals gives exactly A^T's diagonals
+    (cleartext slots, fully replicated layout)."""
+    S = 128
+    rng = np.random.default_rng(m * 31 + n)
+    A = rng.uniform(-1, 1, (m, n))
+    width = max(PL.pow2_ceil(m), PL.pow2_ceil(n))
+    plan = PL.CtMatPlan(m, n, 1, S, pack=S // width)
+    planT = PL.CtMatPlan(n, m, 1, S, pack=S // width)
+    e = [PL.ctmat_ct_slots(plan, A, i) for i in range(plan.ndiag)]
+    for i, (k, r) in enumerate(PL.transpose_map(plan)):
+        assert np.array_equal(np.roll(e[k], -r), PL.ctmat_ct_slots(planT, A.T, i)), (i, k, r)
+
+
+def test_transpose_conversion_as_printed_fails():
+    """the literal Eq. 7 does not give A^T's diagonals for a tall matrix"""
+    S = 64
+    A = np.arange(1, 33, dtype=float).reshape(8, 4)
+    plan = PL.CtMatPlan(8, 4, 1, S, pack=S // 8)
+    planT = PL.CtMatPlan(4, 8, 1, S, pack=S // 8)
+    e = [PL.ctmat_ct_slots(plan, A, i) for i in range(plan.ndiag)]
+    ok = [np.array_equal(np.roll(e[k], -r), PL.ctmat_ct_slots(planT, A.T, i))
+          for i, (k, r) in enumerate(PL.transpose_map_as_printed(plan))]
+    assert not all(ok)
+
+
+@pytest.mark.parametrize("m,n", [(8, 4), (4, 8)])
+def test_transpose_then_backward_product_encrypted(m, n):
+    """[[A]] -> [[A^T]] by Eq. 7, then Alg. 3 with B: decrypts to A^T B."""
+    prm = tiny(6, 2, 1)
+    N, S = prm.N, prm.slots
+    rng = np.random.default_rng(5)
+    A = rng.uniform(-1, 1, (m, n))
+    B = rng.uniform(-1, 1, (m, 3))
+    width = max(m, n)
+    plan = PL.CtMatPlan(m, n, 1, S, pack=S // width)
+    planT = PL.CtMatPlan(n, m, 3, S, pack=S // width)
+    s = O.keygen(prm, 21)
+    keys = {g: O.rotkey_gen(prm, s, g, 22) for g in PL.transpose_galois(plan, N)}
+    cts = [O.encrypt(prm, s, O.encode(PL.ctmat_ct_slots(plan, A, i), N, prm.scale), prm.L, 23 + i)
+           for i in range(plan.ndiag)]
+    ctsT = PL.ctmat_transpose(prm, plan, cts, keys)
+    pts = [O.encode(PL.ctmat_pt_slots(planT, B, i, k), N, prm.scale)
+           for i in range(planT.ndiag) for k in range(planT.n_out_cts)]
+    outs = PL.ctmat_matmul(prm, planT, ctsT, pts)
+    zs = [O.decrypt_decode(prm, s, ct, prm.scale ** 2) for ct in outs]
+    got = PL.ctmat_finish(planT, zs)
+    assert rel_err(got, A.T @ B) < 1e-3

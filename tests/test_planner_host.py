@@ -19,7 +19,7 @@ def test_regret_of_a_choice():
     res = P.regrets(recs, np.array([0.1, 0.2, 9.0, 3.0]))
     assert [s["regret"] for s in res["shapes"]] == [1.0, 0.0]
     assert res["mean"] == 0.5 and res["max"] == 1.0
-    fixed = P.fixed_choice_regret(recs, lambda o: o["kind"] == 0)
+    fixed = P.fixed_choice_regret(recs, lambda r: r["opts"]["kind"] == 0)
     assert [s["regret"] for s in fixed["shapes"]] == [1.0, 0.25]
 
 
@@ -32,6 +32,15 @@ def test_analytic_fit_recovers_known_costs():
         recs.append(_rec("C2", i, 0, float(np.dot(c, true)), c))
     got = P.fit_analytic(recs)["C2"]
     assert np.allclose(got, true, rtol=1e-8, atol=1e-10)
+
+
+def test_digit_count_variants_pool_their_candidates():
+    # the same seeded shape on C4 and on its one-special-prime variant is one choice
+    recs = [_rec("C4", 0, 0, 3.0, [1] * 8), _rec("C4a1", 0, 0, 2.0, [1] * 8), _rec("C3", 0, 0, 1.0, [1] * 8)]
+    res = P.regrets(recs, np.array([0.5, 0.9, 0.1]))
+    assert len(res["shapes"]) == 2
+    c4 = [s for s in res["shapes"] if s["config"] == "C4"][0]
+    assert c4["regret"] == 0.5 and c4["best"].startswith("C4a1")
 
 
 def test_split_holds_out_every_fourth_shape():
