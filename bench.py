@@ -22,6 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP64 vector peak: 256 CUs x 64 FP64 FMA lanes per clock x 2 flops x 2.4 GHz
+FP64_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # timer class -> kernel symbol (template instances share the prefix)
 KERNEL_SYMBOL = {"fused_diagonal": "k_diag_batch", "encode_pt": "k_encode_pt_batch", "modup": "k_modup",
                  "moddown": "k_moddown"}
@@ -72,6 +74,24 @@ def copy_calibration(nbytes=256 << 20, reps=3):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": nbytes, "dispatches": reps}), flush=True)
+
+
+def encode_flops(n_pts: int, pt_limbs: int, log_n: int) -> float:
+    """Algorithmic FP64 operations of encoding n_pts plaintexts of pt_limbs
+    limbs each at ring degree 2^log_n (an FMA counts two):
+    * inverse canonical embedding: an FFT of M = N/2 complex points,
+      5 M log2 M, plus the twist by the 2N-th roots (6 M) and the scaling and
+      rounding of the N real coefficients (2 N);
+    * per limb: reduction of each coefficient modulo q (4 N) and the
+      negacyclic NTT, (N/2) log2 N butterflies of 10 operations each -- the
+      modular product as an exact double-double product (mul + FMA), a
+      quotient estimate (mul, round) and the remainder (FMA + add), then the
+      butterfly's add and subtract."""
+    N = 1 << log_n
+    M = N // 2
+    fft = 5 * M * (log_n - 1) + 6 * M + 2 * N
+    limb = 4 * N + 10 * (N // 2) * log_n
+    return float(n_pts) * (fft + pt_limbs * limb)
 
 
 def measured_traffic(launch_key: str, kernel: str):
@@ -218,7 +238,17 @@ def main():
             f"{by / max(tot_ms, 1e-9) / 1e6:.1f} GB/s algorithmic")
     dom = max(kt, key=lambda k: kt[k]["total_ms"])
     dk = kt[dom]
-    achieved = dk["bytes"] / (dk["total_ms"] * 1e-3) / 1e9 if dk["total_ms"] > 0 else 0.0
+    avg_launch_s = dk["total_ms"] * 1e-3 / max(dk["launches"], 1)
+    if dom == "encode_pt":
+        # FP64-ALU bound: far above the HBM balance point (about 9 flops per byte)
+        infos = [p.info for p in plans]
+        flops = sum(encode_flops(i["n_pts"], i["pt_limbs"], d["logN"]) for i in infos)
+        bound, unit, peak, per_launch = "alu", "TFLOP/s", FP64_PEAK_TFLOPS, flops
+        achieved = flops / avg_launch_s / 1e12
+    else:
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+        per_launch = dk["bytes"] / max(dk["launches"], 1)
+        achieved = per_launch / avg_launch_s / 1e9
     launch_key = f"C3 x{len(shapes)}, group {args.group}, chunk {args.chunk}, vec {args.vec}" + \
         ("" if args.chunk_major else ", slot-major")
     traffic = measured_traffic(launch_key, KERNEL_SYMBOL[dom])
@@ -247,10 +277,11 @@ def main():
                                f"{'' if args.no_graph else ', HIP graph'}",
                    "macs_per_step": macs, "max_rel_err": max(errs),
                    "percall_ms_per_step": ms_percall, "instrumented_ms_per_step": ms_instrumented},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": dk["bytes"] / max(dk["launches"], 1),
-                     "avg_launch_us": dk["total_ms"] * 1e3 / max(dk["launches"], 1)},
+        "roofline": {"bound": bound, "kernel": KERNEL_SYMBOL[dom], "achieved": achieved, "peak": peak,
+                     "unit": unit, "frac": achieved / peak, "traffic": traffic,
+                     ("flops_per_launch" if bound == "alu" else "bytes_per_launch"): per_launch,
+                     "hbm_bytes_per_launch": dk["bytes"] / max(dk["launches"], 1),
+                     "avg_launch_us": avg_launch_s * 1e6},
         "kernels": {k: {"ms_per_step": v["ms_per_step"], "launches_per_step": v["launches"] / args.steps,
                         "algorithmic_GBps": v["bytes"] / max(v["total_ms"] * 1e-3, 1e-12) / 1e9}
                     for k, v in kt.items()},

@@ -104,73 +104,90 @@ __device__ __forceinline__ void fft_dif_half15(double2* a, const double2* __rest
 
 __device__ __forceinline__ int brev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
 
-// value of slot s of plaintext k for the plan (0 outside the matrix)
-__device__ __forceinline__ double pt_slot_value(const EncodeArgs& a, int k, int s) {
-  switch (a.kind) {
-    case 0: {  // HYBRID: block (b, c), diagonal i; slot s = g bn + j
-      // bn, bm and m' are powers of two (zero padding, Sec. 3): shifts and masks
-      const int per = a.col_blocks * a.mprime;
-      const int b = k / per, c = (k >> a.lmp) % a.col_blocks, i = k & (a.mprime - 1);
-      if (a.bsgs > 0) s = (s - (i & -a.bsgs) + a.slots) & (a.slots - 1);  // pre-rotation by the giant step
-      const int g = s >> a.lbn, j = s & (a.bn - 1);
-      const int rr = (g << a.lmp) + (j & (a.mprime - 1));
-      if (rr >= a.bm) return 0.0;
-      const int row = b * a.bm + rr, col = c * a.bn + ((i + j) & (a.bn - 1));
-      return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
-    }
-    case 1: {  // DIAG: Eq. 5 over max(m,n) slots
-      if (s >= a.width) return 0.0;
-      const int row = s & (a.bm - 1), col = (k + s) & (a.bn - 1);
-      return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
-    }
-    case 2: {  // ROW: row k in slots 0..n-1
-      return (s < a.n && k < a.m) ? a.X[(size_t)k * a.ld + s] : 0.0;
-    }
-    case 3: {  // CTMAT: W (n x n_out); plaintext k = i * n_out_cts + kc
-      const int i = k / a.n_out_cts, kc = k % a.n_out_cts;
-      const int blk = s >> a.lw, j = s & (a.width - 1);
-      if (blk >= a.pack) return 0.0;
-      const int r = (i + j) & (a.bn - 1), col = kc * a.pack + blk;
-      return (r < a.n && col < a.n_out) ? a.X[(size_t)r * a.ld + col] : 0.0;
-    }
+// Element of X that slot s of plaintext k holds (a KIND plan), or -1 where the
+// slot is zero (padding, outside the matrix).
+template <int KIND>
+__device__ __forceinline__ long pt_slot_index(const EncodeArgs& a, int k, int s) {
+  if constexpr (KIND == 0) {  // HYBRID: block (b, c), diagonal i; slot s = g bn + j
+    // bn, bm and m' are powers of two (zero padding, Sec. 3): shifts and masks
+    const int per = a.col_blocks * a.mprime;
+    const int b = k / per, c = (k >> a.lmp) % a.col_blocks, i = k & (a.mprime - 1);
+    if (a.bsgs > 0) s = (s - (i & -a.bsgs) + a.slots) & (a.slots - 1);  // pre-rotation by the giant step
+    const int g = s >> a.lbn, j = s & (a.bn - 1);
+    const int rr = (g << a.lmp) + (j & (a.mprime - 1));
+    const int row = b * a.bm + rr, col = c * a.bn + ((i + j) & (a.bn - 1));
+    return (rr < a.bm && row < a.m && col < a.n) ? (long)row * a.ld + col : -1;
+  } else if constexpr (KIND == 1) {  // DIAG: Eq. 5 over max(m,n) slots
+    const int row = s & (a.bm - 1), col = (k + s) & (a.bn - 1);
+    return (s < a.width && row < a.m && col < a.n) ? (long)row * a.ld + col : -1;
+  } else if constexpr (KIND == 2) {  // ROW: row k in slots 0..n-1
+    return (s < a.n && k < a.m) ? (long)k * a.ld + s : -1;
+  } else {  // CTMAT: W (n x n_out); plaintext k = i * n_out_cts + kc
+    const int i = k / a.n_out_cts, kc = k % a.n_out_cts;
+    const int blk = s >> a.lw, j = s & (a.width - 1);
+    const int r = (i + j) & (a.bn - 1), col = kc * a.pack + blk;
+    return (blk < a.pack && r < a.n && col < a.n_out) ? (long)r * a.ld + col : -1;
   }
-  return 0.0;
 }
 
-// value of slot t of input ciphertext c (the encrypted operand)
-__device__ __forceinline__ double ct_slot_value(const EncodeArgs& a, int c, int t) {
-  switch (a.kind) {
-    case 0: {  // HYBRID: column block c of y, period bn
-      const int col = c * a.bn + (t & (a.bn - 1));
-      return col < a.n ? a.X[col] : 0.0;
-    }
-    case 1:
-    case 2: {  // DIAG / ROW: y with period n_pad
-      const int col = t & (a.bn - 1);
-      return col < a.n ? a.X[col] : 0.0;
-    }
-    case 3: {  // CTMAT: diagonal c of A (m x n), replicated over pack blocks
-      const int blk = t >> a.lw, j = t & (a.width - 1);
-      if (blk >= a.pack) return 0.0;
-      const int row = j & (a.bm - 1), col = (c + j) & (a.bn - 1);
-      return (row < a.m && col < a.n) ? a.X[(size_t)row * a.ld + col] : 0.0;
-    }
+// Element of the encrypted operand that slot t of input ciphertext c holds, or -1.
+template <int KIND>
+__device__ __forceinline__ long ct_slot_index(const EncodeArgs& a, int c, int t) {
+  if constexpr (KIND == 0) {  // HYBRID: column block c of y, period bn
+    const int col = c * a.bn + (t & (a.bn - 1));
+    return col < a.n ? col : -1;
+  } else if constexpr (KIND == 1 || KIND == 2) {  // DIAG / ROW: y with period n_pad
+    const int col = t & (a.bn - 1);
+    return col < a.n ? col : -1;
+  } else {  // CTMAT: diagonal c of A (m x n), replicated over pack blocks
+    const int blk = t >> a.lw, j = t & (a.width - 1);
+    const int row = j & (a.bm - 1), col = (c + j) & (a.bn - 1);
+    return (blk < a.pack && row < a.m && col < a.n) ? (long)row * a.ld + col : -1;
   }
-  return 0.0;
+}
+
+// v[u] = scale * (value of slot slot_of(u)), u < CNT.  Every load is issued
+// before any value is used (a zero slot loads X[0], which exists, and selects
+// 0), so the gather pays one memory latency instead of one per slot.
+template <bool CT, int KIND, int CNT, class SlotOf>
+__device__ __forceinline__ void gather_kind(const EncodeArgs& a, int k, double scale, SlotOf slot_of,
+                                            double (&v)[CNT]) {
+  long id[CNT];
+#pragma unroll
+  for (int u = 0; u < CNT; ++u) id[u] = CT ? ct_slot_index<KIND>(a, k, slot_of(u)) : pt_slot_index<KIND>(a, k, slot_of(u));
+  double x[CNT];
+#pragma unroll
+  for (int u = 0; u < CNT; ++u) x[u] = a.X[id[u] < 0 ? 0 : id[u]];
+#pragma unroll
+  for (int u = 0; u < CNT; ++u) v[u] = id[u] < 0 ? 0.0 : x[u] * scale;
+}
+
+template <bool CT, int CNT, class SlotOf>
+__device__ __forceinline__ void gather_slots(const EncodeArgs& a, int k, double scale, SlotOf slot_of,
+                                             double (&v)[CNT]) {
+  switch (a.kind) {
+    case 0: gather_kind<CT, 0>(a, k, scale, slot_of, v); break;
+    case 1: gather_kind<CT, 1>(a, k, scale, slot_of, v); break;
+    case 2: gather_kind<CT, 2>(a, k, scale, slot_of, v); break;
+    default: gather_kind<CT, 3>(a, k, scale, slot_of, v); break;
+  }
 }
 
 // slots -> FFT -> rounded coefficients in registers: mreg[2u] = m_k and
-// mreg[2u+1] = m_(k+N/2) for k = tid + u T, u < M/T.  val(s) is the scaled
-// value of slot s.  At N = 2^15 the first DIF stage (pairs i, i + M/2, owned
+// mreg[2u+1] = m_(k+N/2) for k = tid + u T, u < M/T.  gather(slot_of, v)
+// fills v[u] with the scaled value of slot slot_of(u) for every u of v.  At N = 2^15 the first DIF stage (pairs i, i + M/2, owned
 // by one thread) runs in registers and the two halves in LDS one after the
 // other; half h yields the coefficients with k = h mod 2.
-template <int LOGN, class Val>
-__device__ __forceinline__ void encode_to_regs_v(Val val, double2* z, double* mreg, const EncTabs& et) {
+template <int LOGN, class Gather>
+__device__ __forceinline__ void encode_to_regs_v(Gather gather, double2* z, double* mreg, const EncTabs& et) {
   constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T, PH = M / T;
   const int tid = threadIdx.x;
   const double inv_m = 1.0 / (double)M;
   if constexpr (LOGN <= 14) {
-    for (int s = tid; s < M; s += T) z[cpad(et.slot2f[s])] = make_double2(val(s), 0.0);
+    double v[PH];
+    gather([&](int u) { return tid + u * T; }, v);
+#pragma unroll
+    for (int u = 0; u < PH; ++u) z[cpad(et.slot2f[tid + u * T])] = make_double2(v[u], 0.0);
     __syncthreads();
     fft_dif_lds<LOGN>(z, et.fft_tw, false);
 #pragma unroll
@@ -186,7 +203,9 @@ __device__ __forceinline__ void encode_to_regs_v(Val val, double2* z, double* mr
 #pragma unroll
     for (int u = 0; u < HM / T; ++u) {
       const int i = tid + u * T;
-      const double a0 = val(et.f2slot[i]), b0 = val(et.f2slot[i + HM]);
+      double ab[2];
+      gather([&](int j) { return (int)et.f2slot[i + j * HM]; }, ab);
+      const double a0 = ab[0], b0 = ab[1];
       z[cpad(i)] = make_double2(a0 + b0, 0.0);
       v0[u] = cmul(make_double2(a0 - b0, 0.0), et.fft_tw[i]);
     }
@@ -216,8 +235,7 @@ __device__ __forceinline__ void encode_to_regs_v(Val val, double2* z, double* mr
 template <int LOGN, bool CT>
 __device__ __forceinline__ void encode_to_regs(const EncodeArgs& a, int k, double2* z, double* mreg, const EncTabs& et,
                                                double scale) {
-  encode_to_regs_v<LOGN>([&](int s) { return (CT ? ct_slot_value(a, k, s) : pt_slot_value(a, k, s)) * scale; }, z,
-                         mreg, et);
+  encode_to_regs_v<LOGN>([&](auto slot_of, auto& v) { gather_slots<CT>(a, k, scale, slot_of, v); }, z, mreg, et);
 }
 
 
@@ -232,7 +250,12 @@ __device__ __forceinline__ void encode_pt_body(const EncodeArgs& a, int k, const
   if (a.kind == 2 && k == a.m) {
     // ROW indicator plaintext: 1 in slot 0 at scale q_(l-1)
     const double ind = a.ind_scale;
-    encode_to_regs_v<LOGN>([&](int t) { return t == 0 ? ind : 0.0; }, s2, mreg, et);
+    encode_to_regs_v<LOGN>(
+        [&](auto slot_of, auto& v) {
+#pragma unroll
+          for (int u = 0; u < (int)(sizeof(v) / sizeof(v[0])); ++u) v[u] = slot_of(u) == 0 ? ind : 0.0;
+        },
+        s2, mreg, et);
   } else {
     encode_to_regs<LOGN, false>(a, k, s2, mreg, et, a.scale);
   }

@@ -17,9 +17,11 @@
 // every pass are close to bank-conflict free.
 //
 // Value ranges (q < 2^48): inputs may be any integers with |x| < 2^51.  A
-// twiddle mulmod of |a| <= 2^51 returns |r| < q, so a forward butterfly grows
-// values by less than q; re-centring at least every 7 stages keeps them below
-// q/2 + 7q < 2^51.  The inverse re-centres its sums every second stage.
+// twiddle mulmod of |a| <= 2^51 by a centred twiddle returns |r| <= 0.875 q
+// (its quotient estimate is within 0.875 of the true quotient), so a forward
+// butterfly grows values by at most 0.875 q.  Re-centring (to |x| <= q/2) at
+// least every 9 stages keeps every butterfly input below q/2 + 8 * 0.875 q =
+// 7.5 q < 2^51.  The inverse re-centres its sums every second stage.
 // Outputs are centred.
 #pragma once
 #include "fp64_mod.hpp"
@@ -66,19 +68,32 @@ __device__ __forceinline__ void pass_bases(int (&base)[16 >> S], int ls) {
   }
 }
 
+// Padded addresses of a set: the passes use spans 2^ls with ls = 0 or ls >= 4.
+// For ls >= 4, u 2^ls is a multiple of 16, so lds_pad(base + u 2^ls) =
+// lds_pad(base) + u (2^ls + 2^(ls-4)); for ls = 0 the set lies inside one
+// aligned run of 16 (base is a multiple of the set size), so the padded
+// addresses are consecutive.  Either way one add per element.
+__device__ __forceinline__ int lds_set_step(int ls) { return (1 << ls) + ((1 << ls) >> 4); }
+
 template <int S>
 __device__ __forceinline__ void lds_load_sets(const double* s, double (&x)[16], const int (&base)[16 >> S], int ls) {
+  const int d = lds_set_step(ls);
 #pragma unroll
-  for (int q = 0; q < (16 >> S); ++q)
+  for (int q = 0; q < (16 >> S); ++q) {
+    const double* p = s + lds_pad(base[q]);
 #pragma unroll
-    for (int u = 0; u < (1 << S); ++u) x[q * (1 << S) + u] = s[lds_pad(base[q] + (u << ls))];
+    for (int u = 0; u < (1 << S); ++u) x[q * (1 << S) + u] = p[u * d];
+  }
 }
 template <int S>
 __device__ __forceinline__ void lds_store_sets(double* s, const double (&x)[16], const int (&base)[16 >> S], int ls) {
+  const int d = lds_set_step(ls);
 #pragma unroll
-  for (int q = 0; q < (16 >> S); ++q)
+  for (int q = 0; q < (16 >> S); ++q) {
+    double* p = s + lds_pad(base[q]);
 #pragma unroll
-    for (int u = 0; u < (1 << S); ++u) s[lds_pad(base[q] + (u << ls))] = x[q * (1 << S) + u];
+    for (int u = 0; u < (1 << S); ++u) p[u * d] = x[q * (1 << S) + u];
+  }
 }
 
 // S radix-2 Cooley-Tukey stages lg0 .. lg0+S-1 on the register sets.  A set
@@ -125,13 +140,16 @@ __device__ __forceinline__ void recentre(double (&x)[N], ModQ m) {
 // The result is left in LDS in bit-reversed order, centred: read it with
 // s[lds_pad(perm[t])] after the call (which ends with a barrier).  The call
 // begins with a barrier, so `s` may still be in use by the caller before it.
-// Re-centring: after every 4-stage pass; the short first pass (S0 < 4 stages)
-// is followed by a 4-stage pass before the first re-centring (S0 + 4 <= 7).
+// Re-centring: at the end of a pass when the next pass would take the count
+// of stages since the last re-centring past 9, and after the last pass.  Each
+// pass's twiddles are loaded before the barrier that precedes it, so their
+// latency overlaps the LDS exchange.
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd_regs(double* s, const double (&c)[16], const double* __restrict__ tw, ModQ m) {
   constexpr int S0 = NttShape<LOGN>::S0;
   constexpr int S = S0 > 0 ? S0 : 4;
   double x[16];
+  int since = S == 4 ? 0 : S;  // stages since the last re-centring
   {
     int base[16 >> S];
     pass_bases<LOGN, S>(base, LOGN - S);
@@ -153,7 +171,11 @@ __device__ __forceinline__ void ntt_fwd_regs(double* s, const double (&c)[16], c
     pass_bases<LOGN, 4>(base, ls);
     lds_load_sets<4>(s, x, base, ls);
     ct_pass_regs<LOGN, 4>(x, lg, base, tw, m);
-    recentre(x, m);
+    since += 4;
+    if (lg + 4 >= LOGN || since + 4 > 9) {
+      recentre(x, m);
+      since = 0;
+    }
     lds_store_sets<4>(s, x, base, ls);
     __syncthreads();
   }
@@ -282,7 +304,16 @@ __device__ __forceinline__ void ntt_fwd_regs_out(double* s, const double (&c)[Nt
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
   if constexpr (LOGN <= 14) {
     ntt_fwd_regs<LOGN>(s, c, tw, m);
-    for (int t = threadIdx.x; t < N; t += T) out(t, s[lds_pad(perm[t])]);
+    // groups of OU slots: their permutation entries are loaded together
+    constexpr int OU = 4;
+#pragma unroll 1
+    for (int t0 = threadIdx.x; t0 < N; t0 += OU * T) {
+      uint32_t pe[OU];
+#pragma unroll
+      for (int u = 0; u < OU; ++u) pe[u] = perm[t0 + u * T];
+#pragma unroll
+      for (int u = 0; u < OU; ++u) out(t0 + u * T, s[lds_pad(pe[u])]);
+    }
   } else {
     constexpr int H = 1 << 14;
     const double w0 = tw[0];
