@@ -92,6 +92,10 @@ typedef struct {
                             baby-step/giant-step split of the diagonal sum (Halevi-Shoup 2018; not in the paper):
                             b - 1 hoisted baby rotations, m'/b - 1 giant rotations per block, each giant inner
                             sum brought down by its own ModDown.  0 = every rotation hoisted (Sec. 4, O4). */
+  int32_t unhoisted;     /* HYBRID/DIAG with per-rotation ModDown (lazy_moddown = 0, bsgs = 0): 1 = every rotation
+                            is a complete O3 rotation of the input ciphertext (Sec. 2; automorphism, then its own
+                            ModUp, key inner product and ModDown), the cost profile of GALA's method in Table 2
+                            (m'-1 Rot, 0 HstRot); 0 = hoisted rotations sharing one ModUp (Sec. 4, O4). */
 } pvfl_plan_opts;
 
 typedef struct {

@@ -92,11 +92,17 @@ class HybridPlan:
     def n_pts(self) -> int:
         return self.row_blocks * self.col_blocks * self.mprime
 
-    def op_counts(self) -> dict:
-        """Tables 2 and 3 counts of this plan (lazy RaS: no O3)."""
+    def op_counts(self, unhoisted: bool = False) -> dict:
+        """Tables 2 and 3 counts of this plan (lazy RaS: no O3).  unhoisted:
+        every diagonal rotation a complete O3 rotation of its input ciphertext,
+        once per (row block, column block) term -- Table 2's GALA row."""
         mults = self.n_pts
-        hst = self.col_blocks * (self.mprime - 1)
         adds = mults - self.row_blocks
+        if unhoisted:
+            rot = self.row_blocks * self.col_blocks * (self.mprime - 1)
+            return {"add": adds, "mult": mults, "rot": rot, "hstrot": 0,
+                    "ct_in": self.col_blocks, "ct_out": self.row_blocks}
+        hst = self.col_blocks * (self.mprime - 1)
         return {"add": adds, "mult": mults, "rot": 0, "hstrot": hst,
                 "ct_in": self.col_blocks, "ct_out": self.row_blocks}
 
@@ -359,7 +365,7 @@ def encode_residues(params: O.Params, slots_vec, scale: float, primes) -> np.nda
     return O.reduce_signed(m, primes)
 
 
-def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool) -> list:
+def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool, hoisted: bool = True) -> list:
     """Evaluate the hybrid plan (or any plan given as `terms()`).
 
     cts: input ciphertexts (coefficient domain); pt_ints: integer coefficient
@@ -370,7 +376,11 @@ def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool) 
       rotation finished by its own ModDown;
     lazy: acc = sum_i pt_i^{QP} * (P*phi_i(c0) + u0_i, u1_i) over Q u P and one
       ModDown per output (the i = 0 term uses (P*c0, P*c1)).
+    hoisted = False (eager only): every rotation a complete O3 rotation
+      (automorphism, then its own ModUp; Sec. 2), once per term -- the cost
+      profile of GALA's method (Table 2).
     """
+    assert hoisted or not lazy, "unhoisted rotations are evaluated with per-rotation ModDown"
     N = params.N
     lv = cts[0].level
     Qp = params.q[: lv + 1]
@@ -379,8 +389,9 @@ def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool) 
     terms = plan.terms()
     n_out = max(t[3] for t in terms) + 1
     digits = {}
-    for c in set(t[0] for t in terms):
-        digits[c] = O.modup(params, lv, cts[c].c1)
+    if hoisted:
+        for c in set(t[0] for t in terms):
+            digits[c] = O.modup(params, lv, cts[c].c1)
     if not lazy:
         outs = [O.zero_ct(params, lv) for _ in range(n_out)]
         rot_cache = {}
@@ -388,9 +399,11 @@ def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool) 
             if (c, i) not in rot_cache:
                 if i == 0:
                     rot_cache[(c, i)] = cts[c]
-                else:
+                elif hoisted:
                     g = O.galois_rotl(i, N)
                     rot_cache[(c, i)] = O.hoisted_rotate(params, cts[c], digits[c], keys[g])
+                else:
+                    rot_cache[(c, i)] = O.rotate(params, cts[c], keys[O.galois_rotl(i, N)])
             pt = O.reduce_signed(pt_ints[k], Qp)
             outs[b] = O.ct_add(params, outs[b], O.ct_mul_pt(params, rot_cache[(c, i)], pt))
         return outs
@@ -559,14 +572,15 @@ def row_galois(plan: RowPlan, N: int) -> list:
     return sorted(set(gs))
 
 
-def diag_matmul(params: O.Params, plan: DiagPlan, ct, pt_ints, keys: dict, lazy: bool):
-    """Eq. 5 with hoisted rotations; optional in-ciphertext RaS with O3."""
+def diag_matmul(params: O.Params, plan: DiagPlan, ct, pt_ints, keys: dict, lazy: bool, hoisted: bool = True):
+    """Eq. 5 with hoisted rotations (or, hoisted = False, O3 rotations as in
+    GALA's diagonal method); optional in-ciphertext RaS with O3."""
 
     class _T:
         def terms(self_inner):
             return [(0, i, i, 0) for i in range(plan.ndiag)]
 
-    out = hybrid_matmul(params, _T(), [ct], pt_ints, keys, lazy)[0]
+    out = hybrid_matmul(params, _T(), [ct], pt_ints, keys, lazy, hoisted)[0]
     for k in plan.ras_rotations():
         out = O.ct_add(params, out, O.rotate(params, out, keys[O.galois_rotl(k, params.N)]))
     return out

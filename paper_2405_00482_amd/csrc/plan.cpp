@@ -85,6 +85,11 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
   I.out_log2_scale = lds;
   const bool lazy = o->lazy_moddown != 0;
   if (o->bsgs != 0 && o->kind != PVFL_PLAN_HYBRID) return fail(PVFL_E_PLAN, "bsgs applies to HYBRID plans only");
+  const bool o3 = o->unhoisted != 0;
+  if (o3 && o->kind != PVFL_PLAN_HYBRID && o->kind != PVFL_PLAN_DIAG)
+    return fail(PVFL_E_PLAN, "unhoisted rotations apply to HYBRID and DIAG plans only");
+  if (o3 && (lazy || o->bsgs != 0))
+    return fail(PVFL_E_PLAN, "unhoisted rotations need per-rotation ModDown and no baby-step/giant-step split");
   switch (o->kind) {
     case PVFL_PLAN_HYBRID: {
       const int mp = I.m_pad, np = I.n_pad;
@@ -116,6 +121,12 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
         I.n_rot = (int64_t)I.row_blocks * I.col_blocks * (g - 1);
         I.n_modup = I.col_blocks + (int)I.n_rot;
         I.n_moddown = I.row_blocks * I.col_blocks * g + (int)I.n_rot;
+      } else if (o3) {
+        // every (row block, column block, diagonal i > 0) term rotates its input ciphertext by i
+        for (int i = 1; i < I.mprime; ++i) p->galois.push_back(galois_rotl(i, N));
+        I.n_rot = (int64_t)I.row_blocks * I.col_blocks * (I.mprime - 1);
+        I.n_hstrot = 0;
+        I.n_modup = I.n_moddown = (int)I.n_rot;
       } else {
         for (int i = 1; i < I.mprime; ++i) p->galois.push_back(galois_rotl(i, N));
         I.n_rot = 0;
@@ -149,6 +160,11 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
       I.n_hstrot = nd - 1;
       I.n_modup = (nd > 1 ? 1 : 0) + (int)I.n_rot;
       I.n_moddown = (lazy ? (nd > 1 || c->alpha > 1 ? 1 : 0) : nd - 1) + (int)I.n_rot;
+      if (o3) {  // Table 2, GALA's diagonal: the nd - 1 diagonal rotations become O3
+        I.n_rot += nd - 1;
+        I.n_hstrot = 0;
+        I.n_modup = I.n_moddown = (int)I.n_rot;
+      }
       break;
     }
     case PVFL_PLAN_ROW: {
@@ -263,7 +279,8 @@ static size_t ws_doubles(const pvfl_plan* p) {
         // + 4Q at the end: in-ciphertext RaS temporaries
         return CB * digits + Q + CB * 2 * Q + CB * p->nchunk * 2 * KN + g * 2 * KN + g * ydown + bsgs + 4 * Q;
       }
-      return digits + Q + 2 * KN + ydown + 2 * Q + 4 * Q;
+      // + Q: the rotated c1 of an unhoisted rotation; + 4Q at the end: in-ciphertext RaS temporaries
+      return digits + Q + 2 * KN + ydown + 2 * Q + Q + 4 * Q;
     case PVFL_PLAN_ROW:
       return 8 * Q;
     case PVFL_PLAN_CTMAT:
@@ -437,20 +454,29 @@ static pvfl_status run_diag_eager(const pvfl_plan* p, const double* ct_in, const
   double* u = yup + Q;
   double* ydown = u + 2 * KN;
   double* v = ydown + 2 * (size_t)c->alpha * N;
+  // an unhoisted rotation's phi_i(c1) sits at rct + Q = v + 2Q, past v: ModUp reads
+  // only the c1 half of the ciphertext it is given
+  double* rct = v + Q;
   LaunchCtx L = launch_ctx(c, stream);
   const int mprime = p->info.mprime;
+  const bool o3 = p->opts.unhoisted != 0;
   for (int b = 0; b < p->info.row_blocks; ++b) {
     double* acc = out + (size_t)b * 2 * Q;
     HIP_TRY(launch_fill_zero(L, acc, 2 * Q));
     for (int cb = 0; cb < p->info.col_blocks; ++cb) {
       const double* ct = ct_in + (size_t)cb * 2 * Q;
-      if (mprime > 1) HIP_TRY(launch_modup(L, ct, 0, 1, lv, c->ks_dev + lv, kl.n_tasks, yup, digits, 0));
+      if (mprime > 1 && !o3) HIP_TRY(launch_modup(L, ct, 0, 1, lv, c->ks_dev + lv, kl.n_tasks, yup, digits, 0));
       for (int i = 0; i < mprime; ++i) {
         const double* pt = pts + ((size_t)(b * p->info.col_blocks + cb) * mprime + i) * Q;
         if (i == 0) {
           HIP_TRY(launch_eager_term(L, ct, ct + Q, nullptr, 0, pt, lv, N, acc));
         } else {
-          pvfl_status st = keyswitch_digits(c, keys, lv, digits, i, i, u, ydown, v, stream);
+          if (o3) {
+            // O3: the automorphism first, then this rotation's own ModUp (Sec. 2)
+            HIP_TRY(launch_automorph(L, ct + Q, lv + 1, N, i, rct + Q));
+            HIP_TRY(launch_modup(L, rct, 0, 1, lv, c->ks_dev + lv, kl.n_tasks, yup, digits, 0));
+          }
+          pvfl_status st = keyswitch_digits(c, keys, lv, digits, o3 ? 0 : i, i, u, ydown, v, stream);
           if (st != PVFL_OK) return st;
           HIP_TRY(launch_eager_term(L, ct, nullptr, v, i, pt, lv, N, acc));
         }

@@ -213,6 +213,8 @@ def describe(o: dict) -> str:
     s = kind + ("" if o["kind"] == 2 else (" lazy" if o["lazy_moddown"] else " eager"))
     if o.get("bsgs"):
         s += f" bsgs{o['bsgs']}"
+    if o.get("unhoisted"):
+        s += " O3"
     if o.get("ras_in_ct"):
         s += " ras-in-ct"
     if o.get("batch", 1) > 1:

@@ -44,7 +44,8 @@ COST_NAMES = ("mult", "add", "rot", "hstrot", "modup", "moddown", "pt_limbs", "c
 class PlanOpts(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("n_out", ctypes.c_int32),
                 ("level", ctypes.c_int32), ("lazy_moddown", ctypes.c_int32), ("ras_in_ct", ctypes.c_int32),
-                ("pack", ctypes.c_int32), ("pt_log2_scale", ctypes.c_double), ("bsgs", ctypes.c_int32)]
+                ("pack", ctypes.c_int32), ("pt_log2_scale", ctypes.c_double), ("bsgs", ctypes.c_int32),
+                ("unhoisted", ctypes.c_int32)]
 
 
 class Candidate(ctypes.Structure):
@@ -237,11 +238,13 @@ class Context(_Handle):
     def plan_from(self, o: dict) -> "Plan":
         return self.plan(o["kind"], o["m"], o["n"], n_out=o.get("n_out", 0), level=o.get("level", -1),
                          lazy=bool(o.get("lazy_moddown", 1)), ras_in_ct=bool(o.get("ras_in_ct", 0)),
-                         pack=o.get("pack", 1), pt_log2_scale=o.get("pt_log2_scale", 0.0), bsgs=o.get("bsgs", 0))
+                         pack=o.get("pack", 1), pt_log2_scale=o.get("pt_log2_scale", 0.0), bsgs=o.get("bsgs", 0),
+                         unhoisted=bool(o.get("unhoisted", 0)))
 
     def plan(self, kind: int, m: int, n: int, n_out: int = 0, level: int = -1, lazy: bool = True,
-             ras_in_ct: bool = False, pack: int = 1, pt_log2_scale: float = 0.0, bsgs: int = 0) -> "Plan":
-        o = PlanOpts(kind, m, n, n_out, level, int(lazy), int(ras_in_ct), pack, pt_log2_scale, bsgs)
+             ras_in_ct: bool = False, pack: int = 1, pt_log2_scale: float = 0.0, bsgs: int = 0,
+             unhoisted: bool = False) -> "Plan":
+        o = PlanOpts(kind, m, n, n_out, level, int(lazy), int(ras_in_ct), pack, pt_log2_scale, bsgs, int(unhoisted))
         h = _VP()
         _check(lib().pvfl_plan_create(self.h, ctypes.byref(o), ctypes.byref(h)))
         return Plan(h, self)

@@ -93,6 +93,21 @@ def c5_inputs(cols=None):
     return np.ascontiguousarray(X.T), R
 
 
+# the matrix shapes (m x n) of Table 4, compared at ring degree 2^13
+TABLE4_SHAPES = [(512, 64), (512, 256), (512, 1024), (512, 4096), (64, 512), (256, 512), (1024, 512), (4096, 512),
+                 (64, 64), (256, 256), (1024, 1024), (4096, 4096)]
+
+
+def table4_inputs(m: int, n: int):
+    """X ~ N(0,1) (m x n, standardised columns) and y ~ U[-1,1] (n), seeded by the shape."""
+    g = np.random.default_rng(7000 + 13 * m + n)
+    X = g.standard_normal(size=(m, n))
+    if m > 1:
+        X = (X - X.mean(axis=0)) / X.std(axis=0)
+    y = g.uniform(-1.0, 1.0, size=n)
+    return np.ascontiguousarray(X), y
+
+
 def seeds(name: str) -> dict:
     """Seeds of the counter-based generator for keys and encryption noise."""
     s = seed_of(name)

@@ -145,7 +145,7 @@ def test_rescale_matches_oracle(c1):
 # ---------------------------------------------------------------------------
 # the matrix product
 # ---------------------------------------------------------------------------
-def run_hybrid_both(name, X, y, lazy, kind="hybrid", bsgs=0):
+def run_hybrid_both(name, X, y, lazy, kind="hybrid", bsgs=0, hoisted=True):
     prm = O.Params.from_dict(W.params_dict(name))
     ctx = context(name)
     N = prm.N
@@ -153,13 +153,13 @@ def run_hybrid_both(name, X, y, lazy, kind="hybrid", bsgs=0):
     sk_gpu = ctx.keygen(SEED_SK)
     s = O.keygen(prm, SEED_SK)
     if kind == "hybrid":
-        plan = ctx.plan(0, m, n, lazy=lazy, bsgs=bsgs)
+        plan = ctx.plan(0, m, n, lazy=lazy, bsgs=bsgs, unhoisted=not hoisted)
         oplan = PL.HybridPlan(m, n, prm.slots)
         pts = (PL.bsgs_pt_ints(prm, oplan, X, prm.scale, bsgs) if bsgs
                else PL.hybrid_pt_ints(prm, oplan, X, prm.scale))
         cts_ints = PL.hybrid_ct_ints(prm, oplan, y, prm.scale)
     else:
-        plan = ctx.plan(1, m, n, lazy=lazy, ras_in_ct=(kind == "diag_rot"))
+        plan = ctx.plan(1, m, n, lazy=lazy, ras_in_ct=(kind == "diag_rot"), unhoisted=not hoisted)
         oplan = PL.DiagPlan(m, n, prm.slots, "rot" if kind == "diag_rot" else "lazy")
         pts = [O.encode(PL.diag_pt_slots(oplan, X, i), N, prm.scale) for i in range(oplan.ndiag)]
         cts_ints = [O.encode(PL.diag_ct_slots(oplan, y), N, prm.scale)]
@@ -185,9 +185,9 @@ def run_hybrid_both(name, X, y, lazy, kind="hybrid", bsgs=0):
     if kind == "hybrid" and bsgs:
         want = PL.hybrid_matmul_bsgs(prm, oplan, octs, pts, okeys, bsgs)
     elif kind == "hybrid":
-        want = PL.hybrid_matmul(prm, oplan, octs, pts, okeys, lazy)
+        want = PL.hybrid_matmul(prm, oplan, octs, pts, okeys, lazy, hoisted)
     else:
-        want = [PL.diag_matmul(prm, oplan, octs[0], pts, okeys, lazy)]
+        want = [PL.diag_matmul(prm, oplan, octs[0], pts, okeys, lazy, hoisted)]
     for b, w in enumerate(want):
         assert_same(got[b, 0], w.c0, f"out {b} c0")
         assert_same(got[b, 1], w.c1, f"out {b} c1")
@@ -246,6 +246,35 @@ def test_bsgs_rejects_bad_baby_steps():
         ctx.plan(0, 64, 256, lazy=False, bsgs=2)
     with pytest.raises(pvfl.PvflError):
         ctx.plan(1, 64, 16, lazy=True, bsgs=2)
+
+
+@pytest.mark.parametrize("kind,m,n", [("hybrid", 16, 256), ("hybrid", 100, 37), ("hybrid", 4096, 4), ("hybrid", 4, 4096),
+                                      ("diag", 64, 16), ("diag_rot", 16, 64)])
+def test_unhoisted_bit_exact(kind, m, n):
+    """every rotation a complete O3 rotation (Sec. 2; GALA's cost profile in
+    Table 2): residues equal the oracle's, counts are Table 2's GALA row"""
+    rng = np.random.default_rng(m * 3 + n)
+    X = rng.uniform(-1, 1, (m, n))
+    y = rng.uniform(-1, 1, n)
+    prm, s, outs, oplan = run_hybrid_both("C1", X, y, lazy=False, kind=kind, hoisted=False)
+    ctx = context("C1")
+    if kind == "hybrid":
+        info = ctx.plan(0, m, n, lazy=False, unhoisted=True).info
+        want = oplan.op_counts(unhoisted=True)
+        assert (info["n_rot"], info["n_hstrot"], info["n_mult"]) == (want["rot"], want["hstrot"], want["mult"])
+        zs = [O.decrypt_decode(prm, s, ct, prm.scale ** 2) for ct in outs]
+        got = PL.hybrid_lazy_ras(oplan, zs)
+        assert np.linalg.norm(got - X @ y) / np.linalg.norm(X @ y) < 2.0 ** -18
+
+
+def test_unhoisted_rejects_other_schedules():
+    ctx = context("C1")
+    with pytest.raises(pvfl.PvflError):
+        ctx.plan(0, 64, 256, lazy=True, unhoisted=True)       # O3 rotations are finished one by one
+    with pytest.raises(pvfl.PvflError):
+        ctx.plan(2, 16, 64, lazy=False, unhoisted=True)       # ROW has its own rotations
+    with pytest.raises(pvfl.PvflError):
+        ctx.plan(3, 16, 64, n_out=4, lazy=False, unhoisted=True)
 
 
 @pytest.mark.parametrize("kind,m,n", [("diag", 64, 16), ("diag", 16, 64), ("diag_rot", 16, 64)])

@@ -26,14 +26,14 @@ def tiny(logN, nq, npr, scale_bits=30, q0_bits=40):
     return O.Params(logN=logN, q=out[:nq], p=out[nq:], log2_scale=float(scale_bits))
 
 
-def run_hybrid(prm, X, y, lazy, seed=1):
+def run_hybrid(prm, X, y, lazy, seed=1, hoisted=True):
     N = prm.N
     plan = PL.HybridPlan(X.shape[0], X.shape[1], prm.slots)
     s = O.keygen(prm, seed)
     keys = {g: O.rotkey_gen(prm, s, g, seed + 1) for g in PL.hybrid_galois(plan, N)}
     cts = [O.encrypt(prm, s, m, prm.L, seed + 2 + c) for c, m in enumerate(PL.hybrid_ct_ints(prm, plan, y, prm.scale))]
     pts = PL.hybrid_pt_ints(prm, plan, X, prm.scale)
-    outs = PL.hybrid_matmul(prm, plan, cts, pts, keys, lazy)
+    outs = PL.hybrid_matmul(prm, plan, cts, pts, keys, lazy, hoisted)
     zs = [O.decrypt_decode(prm, s, ct, prm.scale * prm.scale) for ct in outs]
     return PL.hybrid_lazy_ras(plan, zs)
 
@@ -58,6 +58,16 @@ def test_partitioned_hybrid(m, n, logN):
     y = rng.uniform(-1, 1, n)
     for lazy in (True, False):
         assert rel_err(run_hybrid(prm, X, y, lazy), X @ y) < 1e-3
+    # every rotation a complete O3 rotation (GALA's cost profile, Table 2)
+    assert rel_err(run_hybrid(prm, X, y, False, hoisted=False), X @ y) < 1e-3
+
+
+def test_c1_hybrid_unhoisted_precision():
+    """C1 with O3 rotations: the rotation order changes the bits, not the
+    precision class of the per-rotation ModDown plan."""
+    prm = O.Params.from_dict(W.params_dict("C1"))
+    XT, r = W.c1_inputs()
+    assert rel_err(run_hybrid(prm, XT, r, False, hoisted=False), XT @ r) < 2.0 ** -18
 
 
 @pytest.mark.parametrize("m,n", [(16, 4), (4, 16)])
@@ -73,9 +83,10 @@ def test_diag_plan(m, n):
         keys = {g: O.rotkey_gen(prm, s, g, 5) for g in PL.diag_galois(plan, N)}
         ct = O.encrypt(prm, s, O.encode(PL.diag_ct_slots(plan, y), N, prm.scale), prm.L, 6)
         pts = [O.encode(PL.diag_pt_slots(plan, X, i), N, prm.scale) for i in range(plan.ndiag)]
-        out = PL.diag_matmul(prm, plan, ct, pts, keys, lazy=False)
-        z = O.decrypt_decode(prm, s, out, prm.scale ** 2)
-        assert rel_err(PL.diag_finish(plan, z), X @ y) < 1e-3
+        for hoisted in (True, False):
+            out = PL.diag_matmul(prm, plan, ct, pts, keys, lazy=False, hoisted=hoisted)
+            z = O.decrypt_decode(prm, s, out, prm.scale ** 2)
+            assert rel_err(PL.diag_finish(plan, z), X @ y) < 1e-3
 
 
 def test_row_plan_two_rescales():

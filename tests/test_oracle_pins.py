@@ -452,6 +452,9 @@ def test_complexity_tables():
         c = PL.HybridPlan(m, n, S).op_counts()
         k = _m.ceil(m * n / S)
         assert (c["add"], c["mult"], c["rot"], c["hstrot"]) == (k - 1, k, 0, k - 1)
+        # Table 2's GALA row: the same terms with O3 rotations instead of hoisted ones
+        c = PL.HybridPlan(m, n, S).op_counts(unhoisted=True)
+        assert (c["add"], c["mult"], c["rot"], c["hstrot"]) == (k - 1, k, k - 1, 0)
     m, n, S = 64, 8, 8                       # m > N' >= n
     c = PL.HybridPlan(m, n, S).op_counts()
     assert c == {"add": (m * n - m) // S, "mult": m * n // S, "rot": 0, "hstrot": n - 1, "ct_in": 1, "ct_out": m // S}
