@@ -171,6 +171,52 @@ pvfl_status pvfl_encrypt(const pvfl_plan* plan, const pvfl_sk* sk, const double*
 pvfl_status pvfl_decrypt_decode(const pvfl_plan* plan, const pvfl_sk* sk, const void* ct_dev, double* y_dev,
                                 void* stream);
 
+/* Multiplication-level reduction (Sec. 5.2, Eq. 4) and the shares of the
+ * result (Alg. 2).  Eq. 4 rewrites CAESAR's gradient [[g_B]] = (q0 1 - y)^T X
+ * + (q1 X)^T [[z]] + (q2 X)^T [[z^3]]: two ciphertext-plaintext products that
+ * share one layout and one multiplicative level, plus a cleartext term.
+ *
+ * pvfl_encode_pt_scaled: pvfl_encode_pt of coef * X (the q1 X and q2 X of
+ *   Eq. 4); same layout and errors.
+ * pvfl_matmul_ct_pt_sum: out = sum_{k < count} (product of cts[k] and pts[k]),
+ *   every term laid out by `plan`, which must be HYBRID or DIAG with lazy
+ *   ModDown and no baby-step/giant-step split: the terms accumulate over
+ *   Q u P and each output ciphertext takes one ModDown.  cts[k], pts[k]:
+ *   device buffers of pvfl_bytes_ct_in / pvfl_bytes_pt bytes (host array of
+ *   count device pointers); ws: NULL (plan-owned) or at least
+ *   pvfl_bytes_workspace_sum(plan, count) bytes.  Errors: PVFL_E_PLAN for
+ *   other plans, PVFL_E_INVALID for count < 1, PVFL_E_NOKEY, PVFL_E_SHAPE.
+ * pvfl_encode_out: a cleartext as a plaintext at the plan's output level and
+ *   scale (HYBRID, DIAG or CTMAT; no rescale in the plan), layout
+ *   [ct_out][out_level+1][N] (evaluation domain, pvfl_bytes_pt_out bytes).
+ *   The values are encoded at the context scale Delta and the residues
+ *   multiplied by 2^e mod q, e = output exponent - log2(Delta), an integer.
+ *   mode PVFL_OUT_ROWS: v_dev holds the plan's m output values (CTMAT: the
+ *   m x n_out product, row-major); each is split into equal parts over the
+ *   slots that the lazy rotate-and-sum of its row adds up, halving it once per
+ *   rotate-and-sum level (the cleartext inverse RaS of Sec. 5.2), so that
+ *   pvfl_decrypt_decode of ct + pt returns the product plus v.
+ *   mode PVFL_OUT_SLOTS: v_dev holds N/2 slot values per output ciphertext,
+ *   [ct_out][N/2], placed as they are (a mask in the slot domain).
+ * pvfl_out_add_pt: out = ct + sign * pt on the plan's output ciphertexts
+ *   (sign +1 or -1; c1 copied): O1 with a plaintext, e.g. the masking party
+ *   subtracting its random slots (Alg. 2).  out may equal ct.
+ * pvfl_lazy_ras: the lazy rotate-and-sum of Sec. 4.3 over cleartext slot
+ *   vectors [ct_out][N/2] -> the plan's m outputs: the masking party's share
+ *   of the result (Alg. 2, last step). */
+enum { PVFL_OUT_ROWS = 0, PVFL_OUT_SLOTS = 1 };
+pvfl_status pvfl_encode_pt_scaled(const pvfl_plan* plan, const double* X_dev, int64_t ld, double coef, void* pt_dev,
+                                  void* stream);
+pvfl_status pvfl_matmul_ct_pt_sum(const pvfl_plan* plan, int32_t count, const void* const* cts_dev,
+                                  const void* const* pts_dev, const pvfl_rotkeys* keys, void* out_dev, void* ws_dev,
+                                  size_t ws_bytes, void* stream);
+size_t pvfl_bytes_workspace_sum(const pvfl_plan* plan, int32_t count);
+size_t pvfl_bytes_pt_out(const pvfl_plan* plan);
+pvfl_status pvfl_encode_out(const pvfl_plan* plan, const double* v_dev, int32_t mode, void* pt_dev, void* stream);
+pvfl_status pvfl_out_add_pt(const pvfl_plan* plan, const void* ct_dev, const void* pt_dev, int32_t sign,
+                            void* out_dev, void* stream);
+pvfl_status pvfl_lazy_ras(const pvfl_plan* plan, const double* slots_dev, double* y_dev, void* stream);
+
 /* Integer-level entry points (exact residues; used for bit-exact parity).
  * m_dev: int64 coefficient vectors [count][N] on the device.
  * pvfl_pt_import: plaintexts [count][limbs][N] with limbs = level+1 (+alpha if with_p).

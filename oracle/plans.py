@@ -647,3 +647,118 @@ def ctmat_transpose(params: O.Params, plan: CtMatPlan, cts, keys: dict) -> list:
     for k, r in transpose_map(plan):
         out.append(cts[k] if r == 0 else O.rotate(params, cts[k], keys[O.galois_rotl(r, params.N)]))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5.2: multiplication-level reduction (Eq. 4), cleartext inverse RaS,
+# and the masking of the result (Alg. 2)
+# ---------------------------------------------------------------------------
+def eq4_cleartext(q0: float, q1: float, q2: float, z, y, X):
+    """The two sides of Eq. 4 in cleartext: CAESAR's gradient e^T X with
+    e = q0 + q1 z + q2 z^3 - y, and its split (q0 1 - y)^T X + (q1 X)^T z +
+    (q2 X)^T z^3.  X is batch x features."""
+    e = q0 + q1 * z + q2 * z ** 3 - y
+    lhs = e @ X
+    rhs = (q0 * np.ones_like(y) - y) @ X + (q1 * X).T @ z + (q2 * X).T @ z ** 3
+    return lhs, rhs
+
+
+def inverse_ras(values, steps: int) -> np.ndarray:
+    """Cleartext inverse RaS: `steps` rounds of splitting every value into two
+    equal halves and concatenating the two copies, so [M0, M1] becomes
+    [M0/2, M1/2, M0/2, M1/2] -- the paper's [M00, M10, M01, M11] with
+    M_i = M_i0 + M_i1.  Halving is exact in binary64."""
+    u = np.asarray(values, dtype=np.float64)
+    for _ in range(steps):
+        u = np.concatenate([u / 2, u / 2])
+    return u
+
+
+def _log2(x: int) -> int:
+    return x.bit_length() - 1
+
+
+def out_slots(plan, v, ras_in_ct: bool = False) -> list:
+    """Slot vectors, one per output ciphertext, that carry the cleartext v
+    (one value per output, CTMAT: the m x n_out matrix) through the plan's
+    lazy RaS: the result of decrypting ct + encode(slots) and applying the
+    lazy RaS is the product plus v."""
+    S = plan.slots
+    if isinstance(plan, HybridPlan):
+        outs = []
+        for b in range(plan.row_blocks):
+            z = np.zeros(S)
+            for g in range(plan.G):
+                rows = [b * plan.bm + g * plan.mprime + r for r in range(plan.mprime)]
+                vals = [v[r] if r < plan.m else 0.0 for r in rows]
+                z[g * plan.bn:(g + 1) * plan.bn] = inverse_ras(vals, _log2(plan.bn // plan.mprime))
+            outs.append(z)
+        return outs
+    if isinstance(plan, DiagPlan):
+        z = np.zeros(S)
+        if plan.mp >= plan.np_ or ras_in_ct or plan.ras == "rot":
+            z[: plan.m] = v[: plan.m]
+        else:
+            vals = [v[r] if r < plan.m else 0.0 for r in range(plan.mp)]
+            z[: plan.np_] = inverse_ras(vals, _log2(plan.np_ // plan.mp))
+        return [z]
+    if isinstance(plan, CtMatPlan):
+        V = np.asarray(v).reshape(plan.m, plan.nout)
+        outs = []
+        for k in range(plan.n_out_cts):
+            z = np.zeros(S)
+            for blk in range(plan.pack):
+                col = k * plan.pack + blk
+                if col >= plan.nout:
+                    continue
+                if plan.mp >= plan.np_:
+                    z[blk * plan.width: blk * plan.width + plan.m] = V[:, col]
+                else:
+                    vals = [V[r, col] if r < plan.m else 0.0 for r in range(plan.mp)]
+                    z[blk * plan.width: blk * plan.width + plan.np_] = inverse_ras(vals, _log2(plan.np_ // plan.mp))
+            outs.append(z)
+        return outs
+    raise ValueError("no cleartext term for this plan")
+
+
+def encode_at_output(params: O.Params, slots_vec, lv: int, e: int) -> np.ndarray:
+    """A cleartext as a plaintext at scale 2^e * Delta: encoded at Delta, its
+    coefficient residues multiplied by 2^e mod q (Delta * 2^e is the output
+    scale of a product without rescale).  Returns [lv+1][N] residues
+    (coefficient domain)."""
+    m = O.encode(slots_vec, params.N, params.scale)
+    res = O.reduce_signed(m, params.q[: lv + 1])
+    return np.stack([O.poly_scalar(res[i], pow(2, e, q), q) for i, q in enumerate(params.q[: lv + 1])])
+
+
+def ct_add_plain(params: O.Params, ct, pt_res, sign: int):
+    """O1 with a plaintext: (c0 + sign * pt, c1)."""
+    lv = ct.level
+    c0 = np.stack([(O.poly_add if sign > 0 else O.poly_sub)(ct.c0[i], pt_res[i], params.q[i]) for i in range(lv + 1)])
+    return O.Ciphertext(c0, ct.c1.copy(), lv, ct.scale)
+
+
+def hybrid_matmul_sum(params: O.Params, plan, terms: list, keys: dict) -> list:
+    """Eq. 4 on the lazy plan: terms = [(cts, pt_ints)], every pair laid out
+    by `plan`; all terms accumulate over Q u P and every output takes one
+    ModDown."""
+    N = params.N
+    lv = terms[0][0][0].level
+    QPp = params.qp(lv)
+    tl = [(0, i, i, 0) for i in range(plan.ndiag)] if isinstance(plan, DiagPlan) else plan.terms()
+    n_out = max(t[3] for t in tl) + 1
+    acc0 = [np.zeros((len(QPp), N), dtype=np.uint64) for _ in range(n_out)]
+    acc1 = [np.zeros((len(QPp), N), dtype=np.uint64) for _ in range(n_out)]
+    for cts, pt_ints in terms:
+        digits = {c: O.modup(params, lv, cts[c].c1) for c in set(t[0] for t in tl)}
+        cache = {}
+        for (c, i, k, b) in tl:
+            if (c, i) not in cache:
+                cache[(c, i)] = lazy_term(params, cts[c], digits[c], keys, i)
+            t0, t1 = cache[(c, i)]
+            pt = O.reduce_signed(pt_ints[k], QPp)
+            for r, mod in enumerate(QPp):
+                acc0[b][r] = O.poly_add(acc0[b][r], O.poly_mul(pt[r], t0[r], mod), mod)
+                acc1[b][r] = O.poly_add(acc1[b][r], O.poly_mul(pt[r], t1[r], mod), mod)
+    return [O.Ciphertext(O.moddown(params, lv, acc0[b]), O.moddown(params, lv, acc1[b]), lv)
+            for b in range(n_out)]

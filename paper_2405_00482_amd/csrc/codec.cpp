@@ -124,7 +124,13 @@ pvfl_status enc_tables_for(pvfl_ctx* c, EncTabs* et, CrtTabs* crt) {
 }  // namespace pvfl
 
 extern "C" pvfl_status pvfl_encode_pt(const pvfl_plan* p, const double* X, int64_t ld, void* pt, void* stream) {
+  return pvfl_encode_pt_scaled(p, X, ld, 1.0, pt, stream);
+}
+
+extern "C" pvfl_status pvfl_encode_pt_scaled(const pvfl_plan* p, const double* X, int64_t ld, double coef, void* pt,
+                                             void* stream) {
   if (!p || !X || !pt) return fail(PVFL_E_INVALID, "null argument");
+  if (!std::isfinite(coef)) return fail(PVFL_E_INVALID, "coef must be finite");
   pvfl_ctx* c = p->ctx;
   const int need_ld = p->info.kind == PVFL_PLAN_CTMAT ? p->info.n_out : p->info.n;
   if (ld < need_ld) return fail(PVFL_E_SHAPE, "leading dimension smaller than the row length");
@@ -132,7 +138,7 @@ extern "C" pvfl_status pvfl_encode_pt(const pvfl_plan* p, const double* X, int64
   pvfl_status st = enc_tables(c, &h);
   if (st != PVFL_OK) return st;
   EncodeArgs a = geometry_of(p, X, ld);
-  a.scale = p->pt_scale;
+  a.scale = p->pt_scale * coef;
   if (p->info.kind == PVFL_PLAN_ROW) a.ind_scale = (double)c->primes[p->lv - 1];
   LimbMap map = qp_map(c, p->lv, p->info.pt_limbs > p->lv + 1);
   KernelTimer kt(c, stream, PVFL_TIMING_ENCODE, 8.0 * (double)p->info.n_pts * map.n * c->N);
@@ -178,5 +184,68 @@ extern "C" pvfl_status pvfl_decrypt_decode(const pvfl_plan* p, const pvfl_sk* sk
   EncodeArgs a = geometry_of(p, nullptr, 0);
   const int count = p->info.kind == PVFL_PLAN_CTMAT ? p->info.m * p->info.n_out : p->info.m;
   HIP_TRY(launch_readout(L, scratch + res_n, a, p->opts.ras_in_ct, count, y));
+  return PVFL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// cleartexts at the output scale (Sec. 5.2: Eq. 4's cleartext term, Alg. 2's
+// masks) and the masking party's rotate-and-sum
+// ---------------------------------------------------------------------------
+namespace {
+// exponent e with output scale = 2^e * Delta, or -1 when it is not a
+// non-negative integer (a plan with a rescale)
+int out_shift(const pvfl_plan* p) {
+  const double e = p->info.out_log2_scale - p->ctx->log2_scale;
+  const double r = std::nearbyint(e);
+  if (p->info.kind == PVFL_PLAN_ROW || std::fabs(e - r) > 1e-9 || r < 0 || r > 1000) return -1;
+  return (int)r;
+}
+double pow2_mod_centred(int e, uint64_t q) {
+  unsigned __int128 x = 1;
+  for (int i = 0; i < e; ++i) x = (x * 2) % q;
+  const uint64_t r = (uint64_t)x;
+  return r > q / 2 ? (double)r - (double)q : (double)r;
+}
+}  // namespace
+
+extern "C" size_t pvfl_bytes_pt_out(const pvfl_plan* p) {
+  return p ? sizeof(double) * (size_t)p->info.ct_out * (p->info.out_level + 1) * p->ctx->N : 0;
+}
+
+extern "C" pvfl_status pvfl_encode_out(const pvfl_plan* p, const double* v, int32_t mode, void* pt, void* stream) {
+  if (!p || !v || !pt) return fail(PVFL_E_INVALID, "null argument");
+  if (mode != PVFL_OUT_ROWS && mode != PVFL_OUT_SLOTS) return fail(PVFL_E_INVALID, "unknown mode");
+  const int e = out_shift(p);
+  if (e < 0) return fail(PVFL_E_PLAN, "the plan's output scale is not 2^e times the context scale (ROW rescales)");
+  pvfl_ctx* c = p->ctx;
+  EncHost* h;
+  pvfl_status st = enc_tables(c, &h);
+  if (st != PVFL_OK) return st;
+  EncodeArgs a = geometry_of(p, nullptr, 0);
+  a.scale = std::pow(2.0, c->log2_scale);
+  const int lv = p->info.out_level;
+  const LimbMap map = qp_map(c, lv, false);
+  OutFactors fac{};
+  for (int l = 0; l < map.n; ++l) fac.f[l] = pow2_mod_centred(e, c->primes[map.idx[l]]);
+  HIP_TRY(launch_encode_out(launch_ctx(c, stream), a, v, mode, p->opts.ras_in_ct, fac, h->et, map, p->info.ct_out,
+                            (double*)pt));
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_out_add_pt(const pvfl_plan* p, const void* ct, const void* pt, int32_t sign, void* out,
+                                       void* stream) {
+  if (!p || !ct || !pt || !out) return fail(PVFL_E_INVALID, "null argument");
+  if (sign != 1 && sign != -1) return fail(PVFL_E_INVALID, "sign must be +1 or -1");
+  pvfl_ctx* c = p->ctx;
+  HIP_TRY(launch_out_add_pt(launch_ctx(c, stream), (const double*)ct, (const double*)pt, (double)sign, p->info.ct_out,
+                            p->info.out_level, c->N, (double*)out));
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_lazy_ras(const pvfl_plan* p, const double* slots, double* y, void* stream) {
+  if (!p || !slots || !y) return fail(PVFL_E_INVALID, "null argument");
+  EncodeArgs a = geometry_of(p, nullptr, 0);
+  const int count = p->info.kind == PVFL_PLAN_CTMAT ? p->info.m * p->info.n_out : p->info.m;
+  HIP_TRY(launch_readout(launch_ctx(p->ctx, stream), slots, a, p->opts.ras_in_ct, count, y));
   return PVFL_OK;
 }

@@ -31,8 +31,19 @@ struct EncodeArgs {
   int bsgs;          // HYBRID: baby-step size; diagonal i is stored rotated right by (i / bsgs) * bsgs
 };
 
+// per-limb factors (centred residues) of a plaintext encoded at a lower scale
+struct OutFactors {
+  double f[kMaxLimbs];
+};
+
 hipError_t launch_encode_pt(const LaunchCtx& L, const EncodeArgs& a, const EncTabs& et, LimbMap map, int count,
                             double* out);
+// cleartext at the plan's output scale (pvfl_encode_out): out[count][map.n][N]
+hipError_t launch_encode_out(const LaunchCtx& L, const EncodeArgs& a, const double* v, int mode, int ras_in_ct,
+                             const OutFactors& fac, const EncTabs& et, LimbMap map, int count, double* out);
+// out c0 = ct c0 + sign * pt (c1 copied) on nct ciphertexts
+hipError_t launch_out_add_pt(const LaunchCtx& L, const double* ct, const double* pt, double sign, int nct, int lv, int N,
+                             double* out);
 hipError_t launch_encode_ct(const LaunchCtx& L, const EncodeArgs& a, const EncTabs& et, int count, int64_t* msg);
 hipError_t launch_decode(const LaunchCtx& L, const double* res, int nct, int lv, const CrtTabs& ct, const EncTabs& et,
                          double inv_scale, double* z);

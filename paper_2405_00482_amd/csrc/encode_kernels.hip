@@ -108,6 +108,80 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_decode(const double* __re
   }
 }
 
+// Value of slot s of output ciphertext b for a cleartext added to the plan's
+// result (mode 0: the m outputs spread by the cleartext inverse RaS of Sec.
+// 5.2, each split into equal parts over the slots its row's lazy RaS adds;
+// mode 1: slot values [ct_out][N/2] as given).  The parts are powers-of-two
+// fractions of v, so the split is exact.
+__device__ __forceinline__ double out_slot_value(const EncodeArgs& a, const double* __restrict__ v, int mode,
+                                                 int ras_in_ct, int b, int s) {
+  if (mode == 1) return v[(size_t)b * a.slots + s];
+  switch (a.kind) {
+    case 0: {  // HYBRID: slot g bn + j adds into row g m' + (j mod m') of block b
+      const int g = s >> a.lbn, j = s & (a.bn - 1);
+      const int row = b * a.bm + (g << a.lmp) + (j & (a.mprime - 1));
+      return row < a.m ? ldexp(v[row], a.lmp - a.lbn) : 0.0;
+    }
+    case 1: {  // DIAG over max(m,n) slots
+      if (a.bm >= a.bn || ras_in_ct) return s < a.m ? v[s] : 0.0;
+      const int r = s & (a.bm - 1);
+      return (s < a.bn && r < a.m) ? ldexp(v[r], __builtin_ctz(a.bm) - a.lbn) : 0.0;
+    }
+    case 3: {  // CTMAT: output ciphertext b, column block blk = s / width
+      const int blk = s >> a.lw, j = s & (a.width - 1), col = b * a.pack + blk;
+      if (blk >= a.pack || col >= a.n_out) return 0.0;
+      if (a.bm >= a.bn) return j < a.m ? v[(size_t)j * a.n_out + col] : 0.0;
+      const int r = j & (a.bm - 1);
+      return (j < a.bn && r < a.m) ? ldexp(v[(size_t)r * a.n_out + col], __builtin_ctz(a.bm) - a.lbn) : 0.0;
+    }
+  }
+  return 0.0;
+}
+
+// One workgroup per output ciphertext: the cleartext at scale a.scale,
+// rounded, then every limb's residues times fac[l] (2^e mod q) and transformed.
+template <int LOGN>
+__global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_out(EncodeArgs a, const double* __restrict__ v, int mode,
+                                                                  int ras_in_ct, OutFactors fac, EncTabs et, LimbMap map,
+                                                                  DevTabs tb, double* __restrict__ out) {
+  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T, PH = N / 2 / T, PER = NttShape<LOGN>::PER;
+  __shared__ double2 s2[NttShape<LOGN>::LDS / 2];
+  const int b = blockIdx.x;
+  double mreg[2 * PH];
+  encode_to_regs_v<LOGN>(
+      [&](auto slot_of, auto& val) {
+#pragma unroll
+        for (int u = 0; u < (int)(sizeof(val) / sizeof(val[0])); ++u)
+          val[u] = out_slot_value(a, v, mode, ras_in_ct, b, slot_of(u)) * a.scale;
+      },
+      s2, mreg, et);
+  double* s = (double*)s2;
+  for (int l = 0; l < map.n; ++l) {
+    const ModQ m = tb.mods[map.idx[l]];
+    double c[PER];
+#pragma unroll
+    for (int w = 0; w < PER; ++w) c[w] = mulmod(w < PH ? mreg[2 * w] : mreg[2 * (w - PH) + 1], fac.f[l], m);
+    double* dst = out + ((size_t)b * map.n + l) * N;
+    ntt_fwd_regs_out<LOGN>(s, c, tb.fwd_tw + (size_t)map.idx[l] * N, tb.perm, m, [&](int t, double x) { dst[t] = x; });
+  }
+}
+
+// out c0 = ct c0 + sign * pt, c1 copied, on nct ciphertexts of lv+1 limbs
+__global__ __launch_bounds__(256) void k_out_add_pt(const double* __restrict__ ct, const double* __restrict__ pt, double sign,
+                                                    int nct, int lv, int N, const ModQ* __restrict__ mods,
+                                                    double* __restrict__ out) {
+  const size_t Q = (size_t)(lv + 1) * N;
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)nct * 2 * Q) return;
+  const size_t c = idx / (2 * Q), r = idx % (2 * Q);
+  if (r >= Q) {
+    out[idx] = ct[idx];
+    return;
+  }
+  const int i = (int)(r / N);
+  out[idx] = reduce(ct[idx] + sign * pt[c * Q + r], mods[i]);
+}
+
 // lazy rotate-and-sum / read-out of the decoded slots (Sec. 4.3)
 __global__ __launch_bounds__(256) void k_readout(const double* __restrict__ z, EncodeArgs a, int ras_in_ct,
                                                  double* __restrict__ y) {
@@ -154,6 +228,12 @@ static void encode_pt_impl(const LaunchCtx& L, const EncodeArgs& a, const EncTab
   hipLaunchKernelGGL(k_encode_pt<LOGN>, dim3(count), dim3(NttShape<LOGN>::T), 0, L.stream, a, et, map, L.tb, out);
 }
 template <int LOGN>
+static void encode_out_impl(const LaunchCtx& L, const EncodeArgs& a, const double* v, int mode, int ras_in_ct,
+                            const OutFactors& fac, const EncTabs& et, LimbMap map, int count, double* out) {
+  hipLaunchKernelGGL(k_encode_out<LOGN>, dim3(count), dim3(NttShape<LOGN>::T), 0, L.stream, a, v, mode, ras_in_ct, fac,
+                     et, map, L.tb, out);
+}
+template <int LOGN>
 static void encode_ct_impl(const LaunchCtx& L, const EncodeArgs& a, const EncTabs& et, int count, int64_t* msg) {
   hipLaunchKernelGGL(k_encode_ct_msg<LOGN>, dim3(count), dim3(NttShape<LOGN>::T), 0, L.stream, a, et, msg);
 }
@@ -185,6 +265,20 @@ hipError_t launch_encode_ct(const LaunchCtx& L, const EncodeArgs& a, const EncTa
 hipError_t launch_decode(const LaunchCtx& L, const double* res, int nct, int lv, const CrtTabs& ct, const EncTabs& et,
                          double inv_scale, double* z) {
   DISPATCH_LOGN(L, decode_impl, L, res, nct, lv, ct, et, inv_scale, z);
+  return hipGetLastError();
+}
+hipError_t launch_encode_out(const LaunchCtx& L, const EncodeArgs& a, const double* v, int mode, int ras_in_ct,
+                             const OutFactors& fac, const EncTabs& et, LimbMap map, int count, double* out) {
+  if (count <= 0) return hipSuccess;
+  DISPATCH_LOGN(L, encode_out_impl, L, a, v, mode, ras_in_ct, fac, et, map, count, out);
+  return hipGetLastError();
+}
+hipError_t launch_out_add_pt(const LaunchCtx& L, const double* ct, const double* pt, double sign, int nct, int lv, int N,
+                             double* out) {
+  const size_t tot = (size_t)nct * 2 * (lv + 1) * N;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_out_add_pt, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, L.stream, ct, pt, sign, nct, lv, N,
+                     L.tb.mods, out);
   return hipGetLastError();
 }
 hipError_t launch_readout(const LaunchCtx& L, const double* z, const EncodeArgs& a, int ras_in_ct, int count, double* y) {

@@ -265,7 +265,7 @@ extern "C" size_t pvfl_bytes_pt(const pvfl_plan* p) {
 }
 
 // workspace layout (doubles), per plan kind
-static size_t ws_doubles(const pvfl_plan* p) {
+static size_t ws_doubles(const pvfl_plan* p, int count = 1) {
   const pvfl_ctx* c = p->ctx;
   const size_t N = c->N, Q = (size_t)(p->lv + 1) * N, KN = (size_t)p->K * N;
   const size_t digits = (size_t)p->beta * KN;
@@ -274,7 +274,8 @@ static size_t ws_doubles(const pvfl_plan* p) {
     case PVFL_PLAN_HYBRID:
     case PVFL_PLAN_DIAG:
       if (p->opts.lazy_moddown) {
-        const size_t CB = p->info.col_blocks, g = p->info.bsgs ? p->nchunk / p->chunks_per_giant : 1;
+        // every term (count of them) brings col_blocks input ciphertexts
+        const size_t CB = (size_t)count * p->info.col_blocks, g = p->info.bsgs ? p->nchunk / p->chunks_per_giant : 1;
         const size_t bsgs = p->info.bsgs ? g * 2 * Q + digits + 2 * Q + Q : 0;
         // + 4Q at the end: in-ciphertext RaS temporaries
         return CB * digits + Q + CB * 2 * Q + CB * p->nchunk * 2 * KN + g * 2 * KN + g * ydown + bsgs + 4 * Q;
@@ -289,9 +290,12 @@ static size_t ws_doubles(const pvfl_plan* p) {
   return 0;
 }
 extern "C" size_t pvfl_bytes_workspace(const pvfl_plan* p) { return p ? sizeof(double) * std::max<size_t>(ws_doubles(p), 1) : 0; }
+extern "C" size_t pvfl_bytes_workspace_sum(const pvfl_plan* p, int32_t count) {
+  return p && count >= 1 ? sizeof(double) * std::max<size_t>(ws_doubles(p, count), 1) : 0;
+}
 
-static pvfl_status get_ws(const pvfl_plan* p, void* ws, size_t ws_bytes, double** out) {
-  const size_t need = pvfl_bytes_workspace(p);
+static pvfl_status get_ws(const pvfl_plan* p, void* ws, size_t ws_bytes, double** out, int count = 1) {
+  const size_t need = pvfl_bytes_workspace_sum(p, count);
   if (ws) {
     if (ws_bytes < need) return fail(PVFL_E_SHAPE, "workspace too small");
     *out = (double*)ws;
@@ -321,15 +325,22 @@ static pvfl_status check_keys(const pvfl_plan* p, const pvfl_rotkeys* keys) {
 // ---------------------------------------------------------------------------
 // diagonal products (HYBRID, DIAG)
 // ---------------------------------------------------------------------------
-static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const double* pts, const pvfl_rotkeys* keys,
-                                 double* out, double* ws, void* stream) {
+// `count` terms, each an input ciphertext set cts[k] and its plaintexts pts[k]
+// laid out by the plan, summed over Q u P before the ModDown (count > 1: Eq. 4)
+static pvfl_status run_diag_lazy(const pvfl_plan* p, int count, const double* const* cts, const double* const* ptss,
+                                 const pvfl_rotkeys* keys, double* out, double* ws, void* stream) {
   pvfl_ctx* c = p->ctx;
   const int N = c->N, lv = p->lv, K = p->K;
-  const int CB = p->info.col_blocks, RB = p->info.row_blocks;
+  const int CB1 = p->info.col_blocks, CB = count * CB1, RB = p->info.row_blocks;
   const int bs = p->info.bsgs, g = bs ? p->nchunk / p->chunks_per_giant : 1;
   const size_t Q = (size_t)(lv + 1) * N, KN = (size_t)K * N, DG = (size_t)p->beta * KN;
   const KsLevel& kl = c->ks_host[lv];
   // workspace, in the order ws_doubles counts it
+  // input x = k * CB1 + cb: column block cb of term k
+  auto ct_of = [&](int x) { return cts[x / CB1] + (size_t)(x % CB1) * 2 * (lv + 1) * N; };
+  auto pt_of = [&](int b, int x) {
+    return ptss[x / CB1] + (size_t)(b * CB1 + x % CB1) * std::max(1, p->info.mprime) * K * N;
+  };
   double* digits = ws;                                  // [CB][beta][K][N]
   double* yup = digits + CB * DG;                       // [lv+1][N]
   double* pc = yup + Q;                                 // [CB][2][lv+1][N]: P*c of every input
@@ -351,15 +362,15 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
       double* ob = out + (size_t)b * 2 * Q;
       HIP_TRY(launch_fill_zero(L, ob, 2 * Q));
       for (int cb = 0; cb < CB; ++cb) {
-        const double* ct = ct_in + (size_t)cb * 2 * Q;
-        HIP_TRY(launch_eager_term(L, ct, ct + Q, nullptr, 0, pts + (size_t)(b * CB + cb) * KN, lv, N, ob));
+        const double* ct = ct_of(cb);
+        HIP_TRY(launch_eager_term(L, ct, ct + Q, nullptr, 0, pt_of(b, cb), lv, N, ob));
       }
     }
     return PVFL_OK;
   }
   // one ModUp and one P*c per input ciphertext, shared by every row block
   for (int cb = 0; cb < CB; ++cb) {
-    const double* ct = ct_in + (size_t)cb * 2 * Q;
+    const double* ct = ct_of(cb);
     if (mprime > 1) {
       KernelTimer kt(c, stream, PVFL_TIMING_MODUP, 8.0 * (double)(Q + DG));
       HIP_TRY(launch_modup(L, ct, 0, 1, lv, c->ks_dev + lv, kl.n_tasks, yup, digits + cb * DG, 0));
@@ -401,7 +412,7 @@ static pvfl_status run_diag_lazy(const pvfl_plan* p, const double* ct_in, const 
     for (int cb = 0; cb < CB; ++cb) {
       a.digits = digits + cb * DG;
       a.pc = pc + cb * 2 * Q;
-      a.pt = pts + (size_t)(b * CB + cb) * mprime * KN;
+      a.pt = pt_of(b, cb);
       a.part = part + (size_t)z * 2 * KN;
       {
         KernelTimer kt(c, stream, PVFL_TIMING_DIAG, diag_bytes);
@@ -554,7 +565,7 @@ extern "C" pvfl_status pvfl_matmul_ct_pt(const pvfl_plan* p, const void* ct_v, c
   switch (p->opts.kind) {
     case PVFL_PLAN_HYBRID:
     case PVFL_PLAN_DIAG: {
-      st = p->opts.lazy_moddown ? run_diag_lazy(p, ct, pt, keys, out, ws, stream)
+      st = p->opts.lazy_moddown ? run_diag_lazy(p, 1, &ct, &pt, keys, out, ws, stream)
                                 : run_diag_eager(p, ct, pt, keys, out, ws, stream);
       if (st != PVFL_OK) return st;
       if (p->opts.kind == PVFL_PLAN_DIAG && !p->ras_rots.empty()) {
@@ -573,6 +584,29 @@ extern "C" pvfl_status pvfl_matmul_ct_pt(const pvfl_plan* p, const void* ct_v, c
     }
   }
   return fail(PVFL_E_PLAN, "unknown plan kind");
+}
+
+// Eq. 4: the terms of one layout summed over Q u P, one ModDown per output
+extern "C" pvfl_status pvfl_matmul_ct_pt_sum(const pvfl_plan* p, int32_t count, const void* const* cts_v,
+                                             const void* const* pts_v, const pvfl_rotkeys* keys, void* out_v,
+                                             void* ws_v, size_t ws_bytes, void* stream) {
+  if (!p || !cts_v || !pts_v || !out_v) return fail(PVFL_E_INVALID, "null argument");
+  if (count < 1) return fail(PVFL_E_INVALID, "count must be positive");
+  if ((p->opts.kind != PVFL_PLAN_HYBRID && p->opts.kind != PVFL_PLAN_DIAG) || !p->opts.lazy_moddown ||
+      p->info.bsgs != 0 || (p->opts.kind == PVFL_PLAN_DIAG && !p->ras_rots.empty()))
+    return fail(PVFL_E_PLAN, "the summed product needs a HYBRID or DIAG plan with lazy ModDown, no baby-step/giant-step "
+                             "split and no in-ciphertext rotate-and-sum");
+  std::vector<const double*> cts(count), pts(count);
+  for (int k = 0; k < count; ++k) {
+    if (!cts_v[k] || !pts_v[k]) return fail(PVFL_E_INVALID, "null term buffer");
+    cts[k] = (const double*)cts_v[k];
+    pts[k] = (const double*)pts_v[k];
+  }
+  pvfl_status st = check_keys(p, keys);
+  if (st != PVFL_OK) return st;
+  double* ws = nullptr;
+  if ((st = get_ws(p, ws_v, ws_bytes, &ws, count)) != PVFL_OK) return st;
+  return run_diag_lazy(p, count, cts.data(), pts.data(), keys, (double*)out_v, ws, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
 
 PLAN_FEATURES = 27
 OPERAND_CT_VEC, OPERAND_CT_MAT = 0, 1
+OUT_ROWS, OUT_SLOTS = 0, 1
 COST_TERMS = 8
 COST_NAMES = ("mult", "add", "rot", "hstrot", "modup", "moddown", "pt_limbs", "const")
 
@@ -104,6 +105,11 @@ def lib():
             "pvfl_ct_mul_pt": [_VP, i32, _VP, _VP, _VP, _VP],
             "pvfl_ct_add": [_VP, i32, _VP, _VP, _VP, _VP],
             "pvfl_encode_pt": [_VP, _VP, ctypes.c_int64, _VP, _VP],
+            "pvfl_encode_pt_scaled": [_VP, _VP, ctypes.c_int64, ctypes.c_double, _VP, _VP],
+            "pvfl_matmul_ct_pt_sum": [_VP, i32, ctypes.POINTER(_VP), ctypes.POINTER(_VP), _VP, _VP, _VP, sz, _VP],
+            "pvfl_encode_out": [_VP, _VP, i32, _VP, _VP],
+            "pvfl_out_add_pt": [_VP, _VP, _VP, i32, _VP, _VP],
+            "pvfl_lazy_ras": [_VP, _VP, _VP, _VP],
             "pvfl_encrypt": [_VP, _VP, _VP, ctypes.c_int64, u64, _VP, _VP],
             "pvfl_decrypt_decode": [_VP, _VP, _VP, _VP, _VP],
             "pvfl_timing_enable": [_VP, i32],
@@ -139,10 +145,13 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
-        for name in ("pvfl_bytes_ct_in", "pvfl_bytes_ct_out", "pvfl_bytes_pt", "pvfl_bytes_workspace"):
+        for name in ("pvfl_bytes_ct_in", "pvfl_bytes_ct_out", "pvfl_bytes_pt", "pvfl_bytes_workspace",
+                     "pvfl_bytes_pt_out"):
             f = getattr(L, name)
             f.argtypes = [_VP]
             f.restype = sz
+        L.pvfl_bytes_workspace_sum.argtypes = [_VP, i32]
+        L.pvfl_bytes_workspace_sum.restype = sz
         L.pvfl_mlp_num_params.argtypes = [_VP]
         L.pvfl_mlp_num_params.restype = i32
         L.pvfl_plan_num_features.argtypes = []
@@ -322,9 +331,36 @@ class Plan(_Handle):
     def bytes(self, what: str) -> int:
         return int(getattr(lib(), "pvfl_bytes_" + what)(self.h))
 
-    def encode_pt(self, X, out):
-        """X: device float64 matrix (row-major, contiguous rows)."""
-        _check(lib().pvfl_encode_pt(self.h, _ptr(X), X.stride(0) if X.dim() == 2 else X.numel(), _ptr(out), _stream()))
+    def encode_pt(self, X, out, coef: float = 1.0):
+        """X: device float64 matrix (row-major, contiguous rows); coef scales it (Eq. 4's q_1 X)."""
+        ld = X.stride(0) if X.dim() == 2 else X.numel()
+        if coef == 1.0:
+            _check(lib().pvfl_encode_pt(self.h, _ptr(X), ld, _ptr(out), _stream()))
+        else:
+            _check(lib().pvfl_encode_pt_scaled(self.h, _ptr(X), ld, float(coef), _ptr(out), _stream()))
+
+    def matmul_sum(self, cts, pts, keys, out, ws=None):
+        """Eq. 4: out = sum_k product(cts[k], pts[k]) with one ModDown per output"""
+        n = len(cts)
+        ca = (_VP * n)(*[t.data_ptr() for t in cts])
+        pa = (_VP * n)(*[t.data_ptr() for t in pts])
+        ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+        _check(lib().pvfl_matmul_ct_pt_sum(self.h, n, ca, pa, keys.h if keys is not None else None, _ptr(out),
+                                           _ptr(ws), ws_bytes, _stream()))
+
+    def workspace_sum_bytes(self, count: int) -> int:
+        return int(lib().pvfl_bytes_workspace_sum(self.h, count))
+
+    def encode_out(self, v, mode: int, out):
+        """cleartext at the output scale: mode OUT_ROWS (m values, inverse RaS) or OUT_SLOTS ([ct_out][N/2])"""
+        _check(lib().pvfl_encode_out(self.h, _ptr(v), mode, _ptr(out), _stream()))
+
+    def out_add_pt(self, ct, pt, sign: int, out):
+        _check(lib().pvfl_out_add_pt(self.h, _ptr(ct), _ptr(pt), sign, _ptr(out), _stream()))
+
+    def lazy_ras(self, slots, out):
+        """the masking party's share: lazy rotate-and-sum of cleartext slots [ct_out][N/2]"""
+        _check(lib().pvfl_lazy_ras(self.h, _ptr(slots), _ptr(out), _stream()))
 
     def encrypt(self, sk, v, seed: int, out):
         ld = v.stride(0) if v.dim() == 2 else v.numel()
