@@ -56,6 +56,7 @@ typedef enum {
 
 typedef struct pvfl_ctx pvfl_ctx;
 typedef struct pvfl_sk pvfl_sk;
+typedef struct pvfl_pk pvfl_pk;
 typedef struct pvfl_rotkeys pvfl_rotkeys;
 typedef struct pvfl_plan pvfl_plan;
 
@@ -123,6 +124,23 @@ void pvfl_context_destroy(pvfl_ctx* ctx);
 pvfl_status pvfl_keygen(pvfl_ctx* ctx, uint64_t seed, pvfl_sk** out);
 void pvfl_sk_destroy(pvfl_sk* sk);
 
+/* Public key (the public-key form of RLWE encryption; Alg. 2's parties
+ * encrypt with the key owner's public key): pk = (b, a) = (-a s + e, a) over
+ * the L+1 ciphertext primes, a uniform per limb from the stream
+ * (seed, 0x06<<56 | limb), e CBD(21) from (seed, 0x07<<56).  Synchronises.
+ * pvfl_pk_export: canonical uint64 coefficient residues [2][L+1][N] (b, a).
+ * pvfl_encrypt_pk: pvfl_encrypt with the public key: v ternary from
+ *   (seed + k, 0x08<<56), c0 = v b + m + e0, c1 = v a + e1 with e0, e1 CBD(21)
+ *   from (seed + k, 0x09<<56) and (seed + k, 0x0A<<56), ciphertext k.  Its
+ *   noise v e + e0 + e1 s is about sqrt(N) times that of secret-key
+ *   encryption.  Errors as pvfl_encrypt, PVFL_E_INVALID for a key of another
+ *   context.
+ * pvfl_encrypt_coeffs_pk: the same on integer coefficients m_dev [N] at
+ *   `level` (seed used as is), for bit-exact parity. */
+pvfl_status pvfl_pk_gen(pvfl_ctx* ctx, const pvfl_sk* sk, uint64_t seed, pvfl_pk** out);
+void pvfl_pk_destroy(pvfl_pk* pk);
+pvfl_status pvfl_pk_export(const pvfl_pk* pk, uint64_t* out_dev, void* stream);
+
 /* Rotation keys (hybrid key switching) for `count` Galois elements, each a
  * power of 5 modulo 2N (RotL by i slots is 5^i, Sec. 3.1's rotation).  Key
  * memory (count * beta * 2 * (L+1+alpha) * N doubles) is allocated by the
@@ -170,6 +188,8 @@ pvfl_status pvfl_encrypt(const pvfl_plan* plan, const pvfl_sk* sk, const double*
                          void* ct_dev, void* stream);
 pvfl_status pvfl_decrypt_decode(const pvfl_plan* plan, const pvfl_sk* sk, const void* ct_dev, double* y_dev,
                                 void* stream);
+pvfl_status pvfl_encrypt_pk(const pvfl_plan* plan, const pvfl_pk* pk, const double* v_dev, int64_t ld, uint64_t seed,
+                            void* ct_dev, void* stream);
 
 /* Multiplication-level reduction (Sec. 5.2, Eq. 4) and the shares of the
  * result (Alg. 2).  Eq. 4 rewrites CAESAR's gradient [[g_B]] = (q0 1 - y)^T X
@@ -229,6 +249,8 @@ pvfl_status pvfl_pt_import(pvfl_ctx* ctx, int32_t level, int32_t with_p, const i
                            void* pt_dev, void* stream);
 pvfl_status pvfl_encrypt_coeffs(pvfl_ctx* ctx, const pvfl_sk* sk, int32_t level, const int64_t* m_dev, uint64_t seed,
                                 void* ct_dev, void* stream);
+pvfl_status pvfl_encrypt_coeffs_pk(pvfl_ctx* ctx, const pvfl_pk* pk, int32_t level, const int64_t* m_dev,
+                                   uint64_t seed, void* ct_dev, void* stream);
 pvfl_status pvfl_export_coeffs(pvfl_ctx* ctx, int32_t level, int32_t with_p, const void* poly_dev, int32_t count,
                                uint64_t* out_dev, void* stream);
 pvfl_status pvfl_decrypt_coeffs(pvfl_ctx* ctx, const pvfl_sk* sk, int32_t level, const void* ct_dev, uint64_t* out_dev,

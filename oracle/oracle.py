@@ -20,6 +20,8 @@ meet bit for bit; the paper itself only says "Lattigo CKKS", Sec. 6):
       encryption e       (0x03<<56)
       rotation key a_j, limb r (0x04<<56)|(j<<40)|(r<<24)|g   (r indexes Q_L u P)
       rotation key e_j   (0x05<<56)|(j<<40)|g
+      public key a, limb i  (0x06<<56) | i;  public key e (0x07<<56)
+      public-key encryption v (0x08<<56), e0 (0x09<<56), e1 (0x0A<<56)
   uniform mod q = floor(u q / 2^64); ternary = floor(3u / 2^64) - 1;
   error = CBD(21) = popcount(u & (2^21-1)) - popcount((u>>21) & (2^21-1)).
 * Encode (canonical embedding, Cheon et al. 2017):
@@ -152,6 +154,18 @@ def stream_key_a(j: int, r: int, g: int) -> int:
 
 def stream_key_e(j: int, g: int) -> int:
     return (0x05 << 56) | (j << 40) | g
+
+
+def stream_pk_a(limb: int) -> int:
+    return (0x06 << 56) | limb
+
+
+def stream_pk_e() -> int:
+    return 0x07 << 56
+
+
+def stream_pkenc(part: str) -> int:
+    return {"v": 0x08, "e0": 0x09, "e1": 0x0A}[part] << 56
 
 
 def sample_uniform(seed, stream, q, n) -> np.ndarray:
@@ -455,6 +469,38 @@ def encrypt(params: Params, s, m, level: int, seed: int, scale: float = 1.0) -> 
         as_ = poly_mul(a, s_q, q)
         c0[i] = poly_add(poly_sub(mres[i], as_, q), poly_from_signed(e, q), q)
         c1[i] = a
+    return Ciphertext(c0, c1, level, scale)
+
+
+def pk_gen(params: Params, s, seed: int):
+    """Public key (b, a) = (-a s + e, a) over the L+1 ciphertext primes
+    (coefficient domain): the public-key form of RLWE encryption."""
+    N = params.N
+    e = sample_cbd21(seed, stream_pk_e(), N)
+    b, a = [], []
+    for i, q in enumerate(params.q):
+        ai = sample_uniform(seed, stream_pk_a(i), q, N)
+        b.append(poly_add(poly_sub(np.zeros(N, dtype=np.uint64), poly_mul(ai, poly_from_signed(s, q), q), q),
+                          poly_from_signed(e, q), q))
+        a.append(ai)
+    return np.stack(b), np.stack(a)
+
+
+def encrypt_pk(params: Params, pk, m, level: int, seed: int, scale: float = 1.0) -> Ciphertext:
+    """Public-key encryption: v ternary, c0 = v b + m + e0, c1 = v a + e1."""
+    N = params.N
+    b, a = pk
+    v = sample_ternary(seed, stream_pkenc("v"), N)
+    e0 = sample_cbd21(seed, stream_pkenc("e0"), N)
+    e1 = sample_cbd21(seed, stream_pkenc("e1"), N)
+    primes = params.q[: level + 1]
+    mres = reduce_signed(m, primes)
+    c0 = np.zeros((level + 1, N), dtype=np.uint64)
+    c1 = np.zeros((level + 1, N), dtype=np.uint64)
+    for i, q in enumerate(primes):
+        vq = poly_from_signed(v, q)
+        c0[i] = poly_add(poly_add(poly_mul(vq, b[i], q), mres[i], q), poly_from_signed(e0, q), q)
+        c1[i] = poly_add(poly_mul(vq, a[i], q), poly_from_signed(e1, q), q)
     return Ciphertext(c0, c1, level, scale)
 
 

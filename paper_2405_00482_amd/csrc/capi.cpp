@@ -348,6 +348,31 @@ extern "C" pvfl_status pvfl_keygen(pvfl_ctx* c, uint64_t seed, pvfl_sk** out) {
 }
 extern "C" void pvfl_sk_destroy(pvfl_sk* sk) { delete sk; }
 
+pvfl_pk::~pvfl_pk() {
+  if (pk) (void)hipFree(pk);
+}
+extern "C" pvfl_status pvfl_pk_gen(pvfl_ctx* c, const pvfl_sk* sk, uint64_t seed, pvfl_pk** out) {
+  if (!c || !sk || !out) return fail(PVFL_E_INVALID, "null argument");
+  if (sk->ctx != c) return fail(PVFL_E_INVALID, "secret key belongs to another context");
+  std::unique_ptr<pvfl_pk> pk(new pvfl_pk());
+  pk->ctx = c;
+  const int nl = c->n_q;
+  if (hipMalloc((void**)&pk->pk, sizeof(double) * 2 * (size_t)nl * c->N) != hipSuccess)
+    return fail(PVFL_E_NOMEM, "public key allocation");
+  HIP_TRY(launch_pk_gen(launch_ctx(c, nullptr), sk->s, seed, nl, pk->pk));
+  HIP_TRY(hipDeviceSynchronize());
+  *out = pk.release();
+  return PVFL_OK;
+}
+extern "C" void pvfl_pk_destroy(pvfl_pk* pk) { delete pk; }
+extern "C" pvfl_status pvfl_pk_export(const pvfl_pk* pk, uint64_t* out, void* stream) {
+  if (!pk || !out) return fail(PVFL_E_INVALID, "null argument");
+  const pvfl_ctx* c = pk->ctx;
+  LimbMap m = qp_map(c, c->n_q - 1, false);
+  HIP_TRY(launch_ntt(launch_ctx(c, stream), NttOp::ExportU64, pk->pk, out, 2 * m.n, m));
+  return PVFL_OK;
+}
+
 extern "C" pvfl_status pvfl_rotkeys_gen(pvfl_ctx* c, const pvfl_sk* sk, const uint32_t* galois, int32_t count,
                                         uint64_t seed, pvfl_rotkeys** out) {
   if (!c || !sk || !out || (count > 0 && !galois) || count < 0) return fail(PVFL_E_INVALID, "bad argument");
@@ -444,6 +469,15 @@ extern "C" pvfl_status pvfl_encrypt_coeffs(pvfl_ctx* c, const pvfl_sk* sk, int32
   if (!c || !sk || !m || !ct) return fail(PVFL_E_INVALID, "null argument");
   if (bad_level(c, level)) return fail(PVFL_E_LEVEL, "level out of range");
   HIP_TRY(launch_encrypt(launch_ctx(c, stream), m, 1, sk->s, seed, level, (double*)ct));
+  return PVFL_OK;
+}
+
+extern "C" pvfl_status pvfl_encrypt_coeffs_pk(pvfl_ctx* c, const pvfl_pk* pk, int32_t level, const int64_t* m,
+                                              uint64_t seed, void* ct, void* stream) {
+  if (!c || !pk || !m || !ct) return fail(PVFL_E_INVALID, "null argument");
+  if (pk->ctx != c) return fail(PVFL_E_INVALID, "public key belongs to another context");
+  if (bad_level(c, level)) return fail(PVFL_E_LEVEL, "level out of range");
+  HIP_TRY(launch_encrypt_pk(launch_ctx(c, stream), m, 1, pk->pk, c->n_q, seed, level, (double*)ct));
   return PVFL_OK;
 }
 

@@ -54,6 +54,12 @@ struct pvfl_sk {
   ~pvfl_sk();
 };
 
+struct pvfl_pk {
+  pvfl_ctx* ctx = nullptr;
+  double* pk = nullptr;  // [2][L+1][N]: b, then a (evaluation domain)
+  ~pvfl_pk();
+};
+
 struct pvfl_rotkeys {
   pvfl_ctx* ctx = nullptr;
   int key_limbs = 0, beta = 0;

@@ -167,6 +167,27 @@ extern "C" pvfl_status pvfl_encrypt(const pvfl_plan* p, const pvfl_sk* sk, const
   return PVFL_OK;
 }
 
+extern "C" pvfl_status pvfl_encrypt_pk(const pvfl_plan* p, const pvfl_pk* pk, const double* v, int64_t ld,
+                                       uint64_t seed, void* ct, void* stream) {
+  if (!p || !pk || !v || !ct) return fail(PVFL_E_INVALID, "null argument");
+  pvfl_ctx* c = p->ctx;
+  if (pk->ctx != c) return fail(PVFL_E_INVALID, "public key belongs to another context");
+  if (p->info.kind == PVFL_PLAN_CTMAT && ld < p->info.n) return fail(PVFL_E_SHAPE, "leading dimension too small");
+  EncHost* h;
+  pvfl_status st = enc_tables(c, &h);
+  if (st != PVFL_OK) return st;
+  const int nct = p->info.ct_in, N = c->N, lv = p->lv;
+  double* scratch;
+  if ((st = ctx_scratch(c, sizeof(int64_t) * (size_t)nct * N, &scratch)) != PVFL_OK) return st;
+  int64_t* msg = (int64_t*)scratch;
+  EncodeArgs a = geometry_of(p, v, ld);
+  a.scale = std::pow(2.0, c->log2_scale);
+  LaunchCtx L = launch_ctx(c, stream);
+  HIP_TRY(launch_encode_ct(L, a, h->et, nct, msg));
+  HIP_TRY(launch_encrypt_pk(L, msg, nct, pk->pk, c->n_q, seed, lv, (double*)ct));
+  return PVFL_OK;
+}
+
 extern "C" pvfl_status pvfl_decrypt_decode(const pvfl_plan* p, const pvfl_sk* sk, const void* ct, double* y,
                                            void* stream) {
   if (!p || !sk || !ct || !y) return fail(PVFL_E_INVALID, "null argument");

@@ -112,6 +112,56 @@ NTT_KERNEL(LOGN) void k_encrypt(const int64_t* __restrict__ msg, const double* _
     [&](int t, double v) { c0[t] = reduce(v - mulmod(c1[t], sk_i[t], m), m); });
 }
 
+// public key: block i (limb i < nl): a uniform, b = -a s + e (Sec. 2.2, the
+// public-key form of RLWE encryption)
+template <int LOGN>
+NTT_KERNEL(LOGN) void k_pk_gen(const double* __restrict__ sk, uint64_t seed, int nl, double* __restrict__ pk, DevTabs tb) {
+  constexpr int N = 1 << LOGN;
+  NTT_LDS(LOGN);
+  const int i = blockIdx.x;
+  const ModQ m = tb.mods[i];
+  const uint64_t qi = (uint64_t)m.q;
+  double* b = pk + (size_t)i * N;
+  double* a = pk + (size_t)(nl + i) * N;
+  ntt_fwd_out<LOGN>(s, [&](int j) { return sample_uniform_res(seed, kStreamPkA | (uint64_t)i, j, qi); },
+                    tb.fwd_tw + (size_t)i * N, tb.perm, m, [&](int t, double v) { a[t] = v; });
+  const double* sk_i = sk + (size_t)i * N;
+  // slot t of a is read back from what this thread wrote above
+  ntt_fwd_out<LOGN>(s, [&](int j) { return (double)sample_cbd21(seed, kStreamPkE, (uint64_t)j); },
+                    tb.fwd_tw + (size_t)i * N, tb.perm, m,
+                    [&](int t, double v) { b[t] = reduce(v - mulmod(a[t], sk_i[t], m), m); });
+}
+
+// public-key encryption of integer coefficients m at level lv: v ternary,
+// c0 = v b + m + e0, c1 = v a + e1.  Block (c, i): ciphertext c (seed + c), limb i.
+template <int LOGN>
+NTT_KERNEL(LOGN) void k_encrypt_pk(const int64_t* __restrict__ msg, const double* __restrict__ pk, int pk_nl,
+                                    uint64_t seed0, int lv, double* __restrict__ ct_all, DevTabs tb) {
+  constexpr int N = 1 << LOGN;
+  NTT_LDS(LOGN);
+  const int i = blockIdx.x % (lv + 1), c = blockIdx.x / (lv + 1);
+  const uint64_t seed = seed0 + (uint64_t)c;
+  const int64_t* mc = msg + (size_t)c * N;
+  double* ct = ct_all + (size_t)c * 2 * (lv + 1) * N;
+  const ModQ m = tb.mods[i];
+  double* c0 = ct + (size_t)i * N;
+  double* c1 = ct + (size_t)(lv + 1 + i) * N;
+  const double* b = pk + (size_t)i * N;
+  const double* a = pk + (size_t)(pk_nl + i) * N;
+  // v in the evaluation domain, parked in c1; every later read of slot t is by
+  // the thread that wrote it
+  ntt_fwd_out<LOGN>(s, [&](int j) { return (double)sample_ternary(seed, kStreamPkV, (uint64_t)j); },
+                    tb.fwd_tw + (size_t)i * N, tb.perm, m, [&](int t, double v) { c1[t] = v; });
+  const double t32 = tb.two32[i];
+  ntt_fwd_out<LOGN>(s, [&](int j) {
+      return reduce(i64_to_res(mc[j], m, t32) + (double)sample_cbd21(seed, kStreamPkE0, (uint64_t)j), m);
+    }, tb.fwd_tw + (size_t)i * N, tb.perm, m,
+    [&](int t, double v) { c0[t] = reduce(v + mulmod(c1[t], b[t], m), m); });
+  ntt_fwd_out<LOGN>(s, [&](int j) { return (double)sample_cbd21(seed, kStreamPkE1, (uint64_t)j); },
+                    tb.fwd_tw + (size_t)i * N, tb.perm, m,
+                    [&](int t, double v) { c1[t] = reduce(v + mulmod(c1[t], a[t], m), m); });
+}
+
 // c0 + c1 s -> canonical coefficient residues (uint64), block i = limb i
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_decrypt_u64(const double* __restrict__ ct, const double* __restrict__ sk, int lv,
@@ -529,6 +579,27 @@ static void keygen_impl(const LaunchCtx& L, uint64_t seed, double* sk, int n_mod
 }
 hipError_t launch_keygen(const LaunchCtx& L, uint64_t seed, double* sk, int n_mod) {
   DISPATCH_LOGN(L, keygen_impl, L, seed, sk, n_mod);
+  return hipGetLastError();
+}
+
+template <int LOGN>
+static void pk_gen_impl(const LaunchCtx& L, const double* sk, uint64_t seed, int nl, double* pk) {
+  hipLaunchKernelGGL(k_pk_gen<LOGN>, dim3(nl), dim3(NttShape<LOGN>::T), 0, L.stream, sk, seed, nl, pk, L.tb);
+}
+hipError_t launch_pk_gen(const LaunchCtx& L, const double* sk, uint64_t seed, int nl, double* pk) {
+  DISPATCH_LOGN(L, pk_gen_impl, L, sk, seed, nl, pk);
+  return hipGetLastError();
+}
+template <int LOGN>
+static void encrypt_pk_impl(const LaunchCtx& L, const int64_t* msg, int nct, const double* pk, int pk_nl, uint64_t seed,
+                            int lv, double* ct) {
+  hipLaunchKernelGGL(k_encrypt_pk<LOGN>, dim3(nct * (lv + 1)), dim3(NttShape<LOGN>::T), 0, L.stream, msg, pk, pk_nl,
+                     seed, lv, ct, L.tb);
+}
+hipError_t launch_encrypt_pk(const LaunchCtx& L, const int64_t* msg, int nct, const double* pk, int pk_nl,
+                             uint64_t seed, int lv, double* ct) {
+  if (nct <= 0) return hipSuccess;
+  DISPATCH_LOGN(L, encrypt_pk_impl, L, msg, nct, pk, pk_nl, seed, lv, ct);
   return hipGetLastError();
 }
 

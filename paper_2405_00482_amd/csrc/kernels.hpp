@@ -18,6 +18,11 @@ constexpr uint64_t kStreamEncA = 0x02ull << 56;  // | limb
 constexpr uint64_t kStreamEncE = 0x03ull << 56;
 constexpr uint64_t kStreamKeyA = 0x04ull << 56;  // | j<<40 | r<<24 | g
 constexpr uint64_t kStreamKeyE = 0x05ull << 56;  // | j<<40 | g
+constexpr uint64_t kStreamPkA = 0x06ull << 56;   // | limb: public key a
+constexpr uint64_t kStreamPkE = 0x07ull << 56;   // public key error
+constexpr uint64_t kStreamPkV = 0x08ull << 56;   // public-key encryption: ternary v
+constexpr uint64_t kStreamPkE0 = 0x09ull << 56;  // public-key encryption: e0
+constexpr uint64_t kStreamPkE1 = 0x0Aull << 56;  // public-key encryption: e1
 
 struct LimbMap {
   int n;
@@ -79,6 +84,11 @@ struct DiagArgs {
 hipError_t launch_ntt(const LaunchCtx& L, NttOp op, const void* in, void* out, int nblocks, LimbMap map);
 hipError_t launch_keygen(const LaunchCtx& L, uint64_t seed, double* sk, int n_mod);
 // nct ciphertexts [nct][2][lv+1][N] from messages [nct][N]; ciphertext c uses seed + c
+// public key (b, a) = (-a s + e, a) over the nl = L+1 ciphertext primes: pk [2][nl][N]
+hipError_t launch_pk_gen(const LaunchCtx& L, const double* sk, uint64_t seed, int nl, double* pk);
+// public-key encryption at level lv: c = v (b, a) + (m + e0, e1); pk_stride = limbs per pk half
+hipError_t launch_encrypt_pk(const LaunchCtx& L, const int64_t* msg, int nct, const double* pk, int pk_nl,
+                             uint64_t seed, int lv, double* ct);
 hipError_t launch_encrypt(const LaunchCtx& L, const int64_t* msg, int nct, const double* sk, uint64_t seed, int lv,
                           double* ct, double* const* ct_tab = nullptr);
 hipError_t launch_decrypt_u64(const LaunchCtx& L, const double* ct, const double* sk, int lv, uint64_t* out);

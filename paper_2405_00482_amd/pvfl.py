@@ -106,6 +106,10 @@ def lib():
             "pvfl_ct_add": [_VP, i32, _VP, _VP, _VP, _VP],
             "pvfl_encode_pt": [_VP, _VP, ctypes.c_int64, _VP, _VP],
             "pvfl_encode_pt_scaled": [_VP, _VP, ctypes.c_int64, ctypes.c_double, _VP, _VP],
+            "pvfl_pk_gen": [_VP, _VP, u64, ctypes.POINTER(_VP)],
+            "pvfl_pk_export": [_VP, _VP, _VP],
+            "pvfl_encrypt_pk": [_VP, _VP, _VP, ctypes.c_int64, u64, _VP, _VP],
+            "pvfl_encrypt_coeffs_pk": [_VP, _VP, i32, _VP, u64, _VP, _VP],
             "pvfl_matmul_ct_pt_sum": [_VP, i32, ctypes.POINTER(_VP), ctypes.POINTER(_VP), _VP, _VP, _VP, sz, _VP],
             "pvfl_encode_out": [_VP, _VP, i32, _VP, _VP],
             "pvfl_out_add_pt": [_VP, _VP, _VP, i32, _VP, _VP],
@@ -156,7 +160,8 @@ def lib():
         L.pvfl_mlp_num_params.restype = i32
         L.pvfl_plan_num_features.argtypes = []
         L.pvfl_plan_num_features.restype = i32
-        for name in ("pvfl_context_destroy", "pvfl_sk_destroy", "pvfl_rotkeys_destroy", "pvfl_plan_destroy",
+        for name in ("pvfl_context_destroy", "pvfl_sk_destroy", "pvfl_pk_destroy", "pvfl_rotkeys_destroy",
+                     "pvfl_plan_destroy",
                      "pvfl_batch_destroy", "pvfl_mlp_destroy", "pvfl_planner_destroy"):
             f = getattr(L, name)
             f.argtypes = [_VP]
@@ -229,6 +234,11 @@ class Context(_Handle):
         _check(lib().pvfl_keygen(self.h, seed, ctypes.byref(h)))
         return SecretKey(h, keep=(self,))
 
+    def pk_gen(self, sk: "SecretKey", seed: int) -> "PublicKey":
+        h = _VP()
+        _check(lib().pvfl_pk_gen(self.h, sk.h, seed, ctypes.byref(h)))
+        return PublicKey(h, keep=(self,))
+
     def rotkeys(self, sk: "SecretKey", galois, seed: int) -> "RotKeys":
         g = [int(x) for x in galois]
         arr = (ctypes.c_uint32 * max(1, len(g)))(*g)
@@ -275,6 +285,9 @@ class Context(_Handle):
     def encrypt_coeffs(self, sk, level: int, m_i64, seed: int, out):
         _check(lib().pvfl_encrypt_coeffs(self.h, sk.h, level, _ptr(m_i64), seed, _ptr(out), _stream()))
 
+    def encrypt_coeffs_pk(self, pk, level: int, m_i64, seed: int, out):
+        _check(lib().pvfl_encrypt_coeffs_pk(self.h, pk.h, level, _ptr(m_i64), seed, _ptr(out), _stream()))
+
     def export_coeffs(self, level: int, with_p: bool, poly, count: int, out):
         _check(lib().pvfl_export_coeffs(self.h, level, int(with_p), _ptr(poly), count, _ptr(out), _stream()))
 
@@ -299,6 +312,13 @@ class SecretKey(_Handle):
 
     def export(self, out):
         _check(lib().pvfl_sk_export(self.h, _ptr(out), _stream()))
+
+
+class PublicKey(_Handle):
+    _destroy = "pvfl_pk_destroy"
+
+    def export(self, out):
+        _check(lib().pvfl_pk_export(self.h, _ptr(out), _stream()))
 
 
 class RotKeys(_Handle):
@@ -365,6 +385,10 @@ class Plan(_Handle):
     def encrypt(self, sk, v, seed: int, out):
         ld = v.stride(0) if v.dim() == 2 else v.numel()
         _check(lib().pvfl_encrypt(self.h, sk.h, _ptr(v), ld, seed, _ptr(out), _stream()))
+
+    def encrypt_pk(self, pk, v, seed: int, out):
+        ld = v.stride(0) if v.dim() == 2 else v.numel()
+        _check(lib().pvfl_encrypt_pk(self.h, pk.h, _ptr(v), ld, seed, _ptr(out), _stream()))
 
     def decrypt_decode(self, sk, ct, out):
         _check(lib().pvfl_decrypt_decode(self.h, sk.h, _ptr(ct), _ptr(out), _stream()))
