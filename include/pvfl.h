@@ -77,7 +77,9 @@ enum {
   PVFL_PLAN_HYBRID = 0, /* Eq. 5 diagonals + Eq. 6 input packing + partitioning + lazy RaS (Sec. 4) */
   PVFL_PLAN_DIAG = 1,   /* Eq. 5 alone over max(m,n) slots (Sec. 4.1) */
   PVFL_PLAN_ROW = 2,    /* row-order (naive) method (Sec. 3.1) */
-  PVFL_PLAN_CTMAT = 3   /* [[A]] W with A sent as Eq. 5 diagonals (Alg. 3) */
+  PVFL_PLAN_CTMAT = 3,  /* [[A]] W with A sent as Eq. 5 diagonals (Alg. 3) */
+  PVFL_PLAN_COL = 4     /* column-order method (Sec. 3.1): n input ciphertexts, [[y_j]] replicated over every
+                           slot, times column j of X; no rotation (Table 2: n Mult, n-1 Add) */
 };
 
 typedef struct {

@@ -274,6 +274,46 @@ def simulate_row(plan: RowPlan, X, y) -> np.ndarray:
 
 
 @dataclass
+class ColPlan:
+    """Sec. 3.1 column-order method: plaintext j holds column j of X, input
+    ciphertext j holds y_j in every slot; out = sum_j pt_j * ct_j, no rotation.
+    m > N' takes row blocks of N' rows (one output ciphertext each)."""
+    m: int
+    n: int
+    slots: int
+
+    def __post_init__(self):
+        self.mp = pow2_ceil(self.m)
+        self.bm = min(self.mp, self.slots)
+        self.row_blocks = max(1, -(-self.mp // self.slots))
+
+    def op_counts(self) -> dict:
+        rb = self.row_blocks
+        return {"add": (self.n - 1) * rb, "mult": self.n * rb, "rot": 0, "hstrot": 0, "ct_in": self.n, "ct_out": rb}
+
+
+def col_pt_slots(plan: ColPlan, X, j: int, b: int) -> np.ndarray:
+    z = np.zeros(plan.slots)
+    rows = X[b * plan.bm:(b + 1) * plan.bm, j]
+    z[: rows.size] = rows
+    return z
+
+
+def col_ct_slots(plan: ColPlan, y, j: int) -> np.ndarray:
+    return np.full(plan.slots, float(y[j]))
+
+
+def col_finish(plan: ColPlan, zs) -> np.ndarray:
+    return np.array([zs[r // plan.bm][r % plan.bm] for r in range(plan.m)])
+
+
+def simulate_col(plan: ColPlan, X, y) -> np.ndarray:
+    zs = [sum(col_pt_slots(plan, X, j, b) * col_ct_slots(plan, y, j) for j in range(plan.n))
+          for b in range(plan.row_blocks)]
+    return col_finish(plan, zs)
+
+
+@dataclass
 class CtMatPlan:
     """Alg. 3: [[A]] (m x n, encrypted as Eq. 5 diagonals) times W (n x n').
 
@@ -762,3 +802,23 @@ def hybrid_matmul_sum(params: O.Params, plan, terms: list, keys: dict) -> list:
                 acc1[b][r] = O.poly_add(acc1[b][r], O.poly_mul(pt[r], t1[r], mod), mod)
     return [O.Ciphertext(O.moddown(params, lv, acc0[b]), O.moddown(params, lv, acc1[b]), lv)
             for b in range(n_out)]
+
+
+def col_pt_ints(params: O.Params, plan: ColPlan, X, scale: float) -> list:
+    """plaintext j * row_blocks + b: column j, row block b"""
+    return [O.encode(col_pt_slots(plan, X, j, b), params.N, scale)
+            for j in range(plan.n) for b in range(plan.row_blocks)]
+
+
+def col_matmul(params: O.Params, plan: ColPlan, cts, pt_ints) -> list:
+    """out_b = sum_j pt_{j,b} * ct_j (Sec. 3.1, column order)"""
+    lv = cts[0].level
+    Qp = params.q[: lv + 1]
+    outs = []
+    for b in range(plan.row_blocks):
+        acc = O.zero_ct(params, lv)
+        for j in range(plan.n):
+            pt = O.reduce_signed(pt_ints[j * plan.row_blocks + b], Qp)
+            acc = O.ct_add(params, acc, O.ct_mul_pt(params, cts[j], pt))
+        outs.append(acc)
+    return outs

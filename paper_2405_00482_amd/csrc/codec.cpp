@@ -101,6 +101,7 @@ EncodeArgs geometry_of(const pvfl_plan* p, const double* X, int64_t ld) {
     case PVFL_PLAN_DIAG:
     case PVFL_PLAN_CTMAT: a.bm = I.m_pad; a.bn = I.n_pad; a.width = std::max(I.m_pad, I.n_pad); break;
     case PVFL_PLAN_ROW: a.bm = I.m_pad; a.bn = I.n_pad; break;
+    case PVFL_PLAN_COL: a.bm = p->bm; a.bn = p->bn; a.n_out_cts = I.ct_out; break;
   }
   auto lg = [](int x) {
     int r = 0;

@@ -122,11 +122,15 @@ __device__ __forceinline__ long pt_slot_index(const EncodeArgs& a, int k, int s)
     return (s < a.width && row < a.m && col < a.n) ? (long)row * a.ld + col : -1;
   } else if constexpr (KIND == 2) {  // ROW: row k in slots 0..n-1
     return (s < a.n && k < a.m) ? (long)k * a.ld + s : -1;
-  } else {  // CTMAT: W (n x n_out); plaintext k = i * n_out_cts + kc
+  } else if constexpr (KIND == 3) {  // CTMAT: W (n x n_out); plaintext k = i * n_out_cts + kc
     const int i = k / a.n_out_cts, kc = k % a.n_out_cts;
     const int blk = s >> a.lw, j = s & (a.width - 1);
     const int r = (i + j) & (a.bn - 1), col = kc * a.pack + blk;
     return (blk < a.pack && r < a.n && col < a.n_out) ? (long)r * a.ld + col : -1;
+  } else {  // COL: plaintext k = j * row_blocks + b holds rows b bm .. of column j
+    const int j = k / a.n_out_cts, b = k % a.n_out_cts;
+    const int row = b * a.bm + s;
+    return (s < a.bm && row < a.m && j < a.n) ? (long)row * a.ld + j : -1;
   }
 }
 
@@ -139,10 +143,12 @@ __device__ __forceinline__ long ct_slot_index(const EncodeArgs& a, int c, int t)
   } else if constexpr (KIND == 1 || KIND == 2) {  // DIAG / ROW: y with period n_pad
     const int col = t & (a.bn - 1);
     return col < a.n ? col : -1;
-  } else {  // CTMAT: diagonal c of A (m x n), replicated over pack blocks
+  } else if constexpr (KIND == 3) {  // CTMAT: diagonal c of A (m x n), replicated over pack blocks
     const int blk = t >> a.lw, j = t & (a.width - 1);
     const int row = j & (a.bm - 1), col = (c + j) & (a.bn - 1);
     return (blk < a.pack && row < a.m && col < a.n) ? (long)row * a.ld + col : -1;
+  } else {  // COL: ciphertext c holds y_c in every slot
+    return c < a.n ? (long)c : -1;
   }
 }
 
@@ -169,7 +175,8 @@ __device__ __forceinline__ void gather_slots(const EncodeArgs& a, int k, double 
     case 0: gather_kind<CT, 0>(a, k, scale, slot_of, v); break;
     case 1: gather_kind<CT, 1>(a, k, scale, slot_of, v); break;
     case 2: gather_kind<CT, 2>(a, k, scale, slot_of, v); break;
-    default: gather_kind<CT, 3>(a, k, scale, slot_of, v); break;
+    case 3: gather_kind<CT, 3>(a, k, scale, slot_of, v); break;
+    default: gather_kind<CT, 4>(a, k, scale, slot_of, v); break;
   }
 }
 

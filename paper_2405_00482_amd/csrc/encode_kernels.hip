@@ -127,6 +127,10 @@ __device__ __forceinline__ double out_slot_value(const EncodeArgs& a, const doub
       const int r = s & (a.bm - 1);
       return (s < a.bn && r < a.m) ? ldexp(v[r], __builtin_ctz(a.bm) - a.lbn) : 0.0;
     }
+    case 4: {  // COL: slot s of output ciphertext b is row b bm + s
+      const int row = b * a.bm + s;
+      return (s < a.bm && row < a.m) ? v[row] : 0.0;
+    }
     case 3: {  // CTMAT: output ciphertext b, column block blk = s / width
       const int blk = s >> a.lw, j = s & (a.width - 1), col = b * a.pack + blk;
       if (blk >= a.pack || col >= a.n_out) return 0.0;
@@ -207,6 +211,9 @@ __global__ __launch_bounds__(256) void k_readout(const double* __restrict__ z, E
     }
     case 2:
       if (idx < a.m) y[idx] = z[idx];
+      return;
+    case 4:  // COL: row block b of N/2 rows, no rotate-and-sum
+      if (idx < a.m) y[idx] = z[(size_t)(idx / a.bm) * M + idx % a.bm];
       return;
     case 3: {
       if (idx >= a.m * a.n_out) return;

@@ -188,6 +188,21 @@ extern "C" pvfl_status pvfl_plan_create(pvfl_ctx* c, const pvfl_plan_opts* o, pv
       I.out_log2_scale = lds - std::log2((double)c->primes[lv]);
       break;
     }
+    case PVFL_PLAN_COL: {
+      // row blocks of N/2 rows; input ciphertext j carries y_j in every slot
+      if (o->n > 65536) return fail(PVFL_E_SHAPE, "COL sends one ciphertext per column: n <= 65536");
+      I.mprime = 1;
+      I.row_blocks = std::max(1, (I.m_pad + S - 1) / S);
+      I.col_blocks = 1;
+      p->bm = std::min(I.m_pad, S);
+      p->bn = I.n_pad;
+      I.ct_in = o->n;
+      I.ct_out = I.row_blocks;
+      I.n_pts = I.ct_in * I.ct_out;
+      I.n_mult = I.n_pts;
+      I.n_add = (int64_t)(o->n - 1) * I.row_blocks;
+      break;
+    }
     case PVFL_PLAN_CTMAT: {
       const int mp = I.m_pad, np = I.n_pad;
       const int width = std::max(mp, np);
@@ -285,6 +300,7 @@ static size_t ws_doubles(const pvfl_plan* p, int count = 1) {
     case PVFL_PLAN_ROW:
       return 8 * Q;
     case PVFL_PLAN_CTMAT:
+    case PVFL_PLAN_COL:
       return 0;
   }
   return 0;
@@ -577,7 +593,9 @@ extern "C" pvfl_status pvfl_matmul_ct_pt(const pvfl_plan* p, const void* ct_v, c
     }
     case PVFL_PLAN_ROW:
       return run_row(p, ct, pt, keys, out, ws, stream);
-    case PVFL_PLAN_CTMAT: {
+    case PVFL_PLAN_CTMAT:
+    case PVFL_PLAN_COL: {
+      // both are out[k] = sum_i ct[i] * pt[i][k] (COL: i = column j, k = row block)
       LaunchCtx L = launch_ctx(p->ctx, stream);
       HIP_TRY(launch_ctmat(L, ct, pt, p->info.ct_in, p->info.ct_out, p->lv, p->ctx->N, out));
       return PVFL_OK;

@@ -397,3 +397,63 @@ def test_transposed_conversion_rejects_partial_packing():
     plan = ctx.plan(pvfl.PLAN_CTMAT, 16, 4, n_out=1, pack=1)
     with pytest.raises(pvfl.PvflError):
         plan.transpose_galois()
+
+
+@pytest.mark.parametrize("m,n", [(16, 8), (100, 37), (4096, 3)])
+def test_column_order_bit_exact(m, n):
+    """Sec. 3.1's column-order method (n input ciphertexts, no rotation):
+    residues equal the oracle's; counts are Table 2's column-order row"""
+    prm = O.Params.from_dict(W.params_dict("C1"))
+    ctx = context("C1")
+    N, lv = prm.N, prm.L
+    rng = np.random.default_rng(m * 11 + n)
+    X = rng.uniform(-1, 1, (m, n))
+    y = rng.uniform(-1, 1, n)
+    plan = ctx.plan(4, m, n)
+    oplan = PL.ColPlan(m, n, prm.slots)
+    info = plan.info
+    want_counts = oplan.op_counts()
+    assert (info["n_mult"], info["n_add"], info["n_rot"], info["n_hstrot"], info["ct_in"], info["ct_out"]) == (
+        want_counts["mult"], want_counts["add"], 0, 0, n, oplan.row_blocks)
+    sk = ctx.keygen(SEED_SK)
+    s = O.keygen(prm, SEED_SK)
+    ct = dev_f64(plan.bytes("ct_in") // 8)
+    octs = []
+    for j in range(n):
+        mi = O.encode(PL.col_ct_slots(oplan, y, j), N, prm.scale)
+        one = dev_f64(2 * (lv + 1) * N)
+        ctx.encrypt_coeffs(sk, lv, dev_i64(mi), SEED_ENC + j, one)
+        ct[j * 2 * (lv + 1) * N:(j + 1) * 2 * (lv + 1) * N] = one
+        octs.append(O.encrypt(prm, s, mi, lv, SEED_ENC + j))
+    pts = PL.col_pt_ints(prm, oplan, X, prm.scale)
+    pt = dev_f64(plan.bytes("pt") // 8)
+    ctx.pt_import(lv, False, dev_i64(np.stack(pts)), pt)
+    out = dev_f64(plan.bytes("ct_out") // 8)
+    plan.matmul(ct, pt, None, out)
+    got = export_ct(ctx, lv, out, info["ct_out"])
+    want = PL.col_matmul(prm, oplan, octs, pts)
+    for b, w in enumerate(want):
+        assert_same(got[b, 0], w.c0, f"out {b} c0")
+        assert_same(got[b, 1], w.c1, f"out {b} c1")
+
+
+def test_column_order_real_path():
+    """encode, encrypt (one ciphertext per column), product, decrypt and read
+    out on the GPU: within 2^-20 of X y"""
+    import torch
+    ctx = context("C1")
+    XT, r = W.c1_inputs()
+    m, n = XT.shape
+    f64 = dict(dtype=torch.float64, device="cuda")
+    plan = ctx.plan(4, m, n)
+    sk = ctx.keygen(SEED_SK)
+    pt = torch.empty(plan.bytes("pt") // 8, **f64)
+    plan.encode_pt(torch.from_numpy(XT).to(**f64), pt)
+    ct = torch.empty(plan.bytes("ct_in") // 8, **f64)
+    plan.encrypt(sk, torch.from_numpy(r).to(**f64), SEED_ENC, ct)
+    out = torch.empty(plan.bytes("ct_out") // 8, **f64)
+    plan.matmul(ct, pt, None, out)
+    y = torch.empty(m, **f64)
+    plan.decrypt_decode(sk, out, y)
+    ref = XT @ r
+    assert np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref) < 2.0 ** -20

@@ -221,3 +221,24 @@ def test_transpose_then_backward_product_encrypted(m, n):
     zs = [O.decrypt_decode(prm, s, ct, prm.scale ** 2) for ct in outs]
     got = PL.ctmat_finish(planT, zs)
     assert rel_err(got, A.T @ B) < 1e-3
+
+
+@pytest.mark.parametrize("m,n", [(16, 8), (100, 5), (64, 3)])
+def test_column_order_plan(m, n):
+    """Sec. 3.1's column-order method: the layout simulator is X y, Table 2's
+    counts hold, and the encrypted product decrypts to X y"""
+    prm = tiny(5, 2, 1)
+    N = prm.N
+    rng = np.random.default_rng(m + n)
+    X = rng.uniform(-1, 1, (m, n))
+    y = rng.uniform(-1, 1, n)
+    plan = PL.ColPlan(m, n, prm.slots)
+    np.testing.assert_allclose(PL.simulate_col(plan, X, y), X @ y, atol=1e-12)
+    c = plan.op_counts()
+    assert (c["mult"], c["add"], c["rot"], c["hstrot"], c["ct_in"]) == (
+        n * plan.row_blocks, (n - 1) * plan.row_blocks, 0, 0, n)
+    s = O.keygen(prm, 4)
+    cts = [O.encrypt(prm, s, O.encode(PL.col_ct_slots(plan, y, j), N, prm.scale), prm.L, 10 + j) for j in range(n)]
+    outs = PL.col_matmul(prm, plan, cts, PL.col_pt_ints(prm, plan, X, prm.scale))
+    zs = [O.decrypt_decode(prm, s, ct, prm.scale ** 2) for ct in outs]
+    assert rel_err(PL.col_finish(plan, zs), X @ y) < 1e-3
