@@ -66,6 +66,53 @@ def cpu_baseline(name, shapes, n_diag, seeds):
                       f"{dt:.1f} s single-threaded; rotation-key generation excluded"}
 
 
+def ctmat_c4(reps: int = 5) -> dict:
+    """The encrypted-matrix operand form at its configuration (N = 2^14, 6+3
+    primes): [[H]] (256 x 64) W (64 x 256), and the backward [[delta]] (256 x
+    256) W^T, by Alg. 3 with the widest column packing (N/2 / max(m, n)).  Times
+    the evaluating party's work per call -- encoding W and the product -- with
+    HIP events (median of reps) and checks the decrypted product."""
+    import torch
+    from paper_2405_00482_amd import pvfl
+    from paper_2405_00482_amd import workloads as W
+    ctx = pvfl.Context.from_dict(W.params_dict("C4"), device=0)
+    seeds = W.seeds("C4")
+    sk = ctx.keygen(seeds["sk"])
+    H, Wm, delta = W.c4_inputs()
+    f64 = dict(dtype=torch.float64, device="cuda:0")
+    out = {}
+    for name, A, B in (("forward", H, Wm), ("backward", delta, np.ascontiguousarray(Wm.T))):
+        m, n = A.shape
+        nout = B.shape[1]
+        pack = (ctx.N // 2) // max(m, n)
+        plan = ctx.plan(pvfl.PLAN_CTMAT, m, n, n_out=nout, pack=pack)
+        Bd = torch.from_numpy(B).to(**f64)
+        pt = torch.empty(plan.bytes("pt") // 8, **f64)
+        ct = torch.empty(plan.bytes("ct_in") // 8, **f64)
+        o = torch.empty(plan.bytes("ct_out") // 8, **f64)
+        y = torch.empty(m * nout, **f64)
+        plan.encrypt(sk, torch.from_numpy(A).to(**f64), seeds["enc"], ct)
+        ts = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.encode_pt(Bd, pt)
+            plan.matmul(ct, pt, None, o)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts[1:]))
+        plan.decrypt_decode(sk, o, y)
+        ref = A @ B
+        err = float(np.linalg.norm(y.cpu().numpy().reshape(m, nout) - ref) / np.linalg.norm(ref))
+        assert err < 2.0 ** -20, f"C4 {name}: decrypted product off by {err}"
+        out[name] = {"shape": f"[[{m}x{n}]] x {n}x{nout}", "pack": pack, "ms": ms,
+                     "mac_per_s": m * n * nout / (ms * 1e-3), "rel_err": err}
+        log(f"[bench] C4 {name}: {m}x{n} times {n}x{nout}, pack {pack}: {ms:.3f} ms, "
+            f"{m * n * nout / (ms * 1e-3):.3e} MAC/s, rel err 2^{np.log2(err):.1f}")
+    return out
+
+
 def copy_calibration(nbytes=256 << 20, reps=3):
     import torch
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
@@ -121,6 +168,7 @@ def main():
     ap.add_argument("--products", type=int, default=64)
     ap.add_argument("--cpu-diagonals", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c4", action="store_true", help="skip the encrypted-matrix (Alg. 3) measurement at C4")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--group", type=int, default=None, help="default: the tuner database's choice, else 2")
     ap.add_argument("--vec", type=int, default=None, help="default: the tuner database's choice, else 1")
@@ -286,6 +334,8 @@ def main():
                         "algorithmic_GBps": v["bytes"] / max(v["total_ms"] * 1e-3, 1e-12) / 1e9}
                     for k, v in kt.items()},
     }
+    if not args.no_c4:
+        result["c4_ctmat"] = ctmat_c4()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(name, shapes, args.cpu_diagonals, seeds)

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpvfl.so")
 
-PLAN_HYBRID, PLAN_DIAG, PLAN_ROW, PLAN_CTMAT = 0, 1, 2, 3
+PLAN_HYBRID, PLAN_DIAG, PLAN_ROW, PLAN_CTMAT, PLAN_COL = 0, 1, 2, 3, 4
 TIMING_DIAG, TIMING_ENCODE, TIMING_MODUP, TIMING_MODDOWN = 0, 1, 2, 3
 
 _STATUS = {0: "OK", -1: "PVFL_E_INVALID", -2: "PVFL_E_SHAPE", -3: "PVFL_E_LEVEL", -4: "PVFL_E_NOKEY",
