@@ -300,6 +300,17 @@ def main():
     launch_key = f"C3 x{len(shapes)}, group {args.group}, chunk {args.chunk}, vec {args.vec}" + \
         ("" if args.chunk_major else ", slot-major")
     traffic = measured_traffic(launch_key, KERNEL_SYMBOL[dom])
+    # the key-switch kernel (fused diagonal: rotations' key inner products and the
+    # plaintext products) against HBM, whichever kernel dominates
+    kd = kt["fused_diagonal"]
+    kd_s = kd["total_ms"] * 1e-3 / max(kd["launches"], 1)
+    kd_bytes = kd["bytes"] / max(kd["launches"], 1)
+    kd_traffic = measured_traffic(launch_key, KERNEL_SYMBOL["fused_diagonal"])
+    roofline_ks = {"bound": "hbm", "kernel": KERNEL_SYMBOL["fused_diagonal"],
+                   "achieved": kd_bytes / kd_s / 1e9 if kd_s > 0 else 0.0, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": (kd_bytes / kd_s / 1e9 / HBM_PEAK_GBS) if kd_s > 0 else 0.0, "traffic": kd_traffic,
+                   "bytes_per_launch": kd_bytes, "avg_launch_us": kd_s * 1e6,
+                   "traffic_GBps": (kd_traffic / kd_s / 1e9) if (kd_traffic and kd_s > 0) else None}
     ms_percall = None
     if args.percall_steps > 0:
         ms_percall = timed(step_percall, args.percall_steps)
@@ -330,6 +341,7 @@ def main():
                      ("flops_per_launch" if bound == "alu" else "bytes_per_launch"): per_launch,
                      "hbm_bytes_per_launch": dk["bytes"] / max(dk["launches"], 1),
                      "avg_launch_us": avg_launch_s * 1e6},
+        "roofline_keyswitch": roofline_ks,
         "kernels": {k: {"ms_per_step": v["ms_per_step"], "launches_per_step": v["launches"] / args.steps,
                         "algorithmic_GBps": v["bytes"] / max(v["total_ms"] * 1e-3, 1e-12) / 1e9}
                     for k, v in kt.items()},
