@@ -38,6 +38,7 @@ __device__ __forceinline__ void fft_pass(double2* a, const double2* __restrict__
   constexpr int LS = LOGM - S0 - S;  // log2 stride
   constexpr unsigned stride = 1u << LS;
   const unsigned tid = threadIdx.x;
+  if (tid < (unsigned)T) {  // a transform of M < 8 * blockDim points leaves the other threads idle
   int base[NS], off[NS];
   double2 x[8];
 #pragma unroll
@@ -69,6 +70,7 @@ __device__ __forceinline__ void fft_pass(double2* a, const double2* __restrict__
   for (int q = 0; q < NS; ++q)
 #pragma unroll
     for (int u = 0; u < SET; ++u) a[cpad(base[q] + (u << LS))] = x[q * SET + u];
+  }
   __syncthreads();
 }
 
@@ -191,18 +193,33 @@ __device__ __forceinline__ void encode_to_regs_v(Gather gather, double2* z, doub
   const int tid = threadIdx.x;
   const double inv_m = 1.0 / (double)M;
   if constexpr (LOGN <= 14) {
-    double v[PH];
-    gather([&](int u) { return tid + u * T; }, v);
+    // The DFT input x[f] (slot value at f = f_j) is real: pack y[n] = x[2n] +
+    // i x[2n+1], transform M/2 points, and split (real-input FFT):
+    //   E[k] = (Y[k] + conj Y[M/2-k]) / 2,  O[k] = (Y[k] - conj Y[M/2-k]) / 2i,
+    //   X[k] = E[k] + W^k O[k],  X[k + M/2] = E[k] - W^k O[k],  W = exp(-2 pi i / M).
+    // The half transform runs on the first half of the threads with every
+    // other twiddle of the M-point table.
+    constexpr int HM = M / 2, QH = HM / T;  // QH = 4 complex inputs per thread
+    double v[2 * QH];
+    gather([&](int u) { return (int)et.f2slot[2 * (tid + (u >> 1) * T) + (u & 1)]; }, v);
 #pragma unroll
-    for (int u = 0; u < PH; ++u) z[cpad(et.slot2f[tid + u * T])] = make_double2(v[u], 0.0);
+    for (int u = 0; u < QH; ++u) z[cpad(tid + u * T)] = make_double2(v[2 * u], v[2 * u + 1]);
     __syncthreads();
-    fft_dif_lds<LOGN>(z, et.fft_tw, false);
+    fft_passes<LOGN - 1, 0, 1>(z, et.fft_tw, false);
 #pragma unroll
-    for (int u = 0; u < PH; ++u) {
-      const int kk = tid + u * T;
-      const double2 w = cmul(z[cpad(brev(kk, LOGN - 1))], cconj(et.twist[kk]));
-      mreg[2 * u] = round_half_away(w.x * inv_m);
-      mreg[2 * u + 1] = round_half_away(w.y * inv_m);
+    for (int u = 0; u < QH; ++u) {
+      const int k = tid + u * T;
+      const double2 Yk = z[cpad(brev(k, LOGN - 2))];
+      const double2 Yc = z[cpad(brev((HM - k) & (HM - 1), LOGN - 2))];
+      const double2 E = make_double2(0.5 * (Yk.x + Yc.x), 0.5 * (Yk.y - Yc.y));
+      const double2 O = make_double2(0.5 * (Yk.y + Yc.y), -0.5 * (Yk.x - Yc.x));
+      const double2 wo = cmul(O, et.fft_tw[k]);
+      const double2 w0 = cmul(make_double2(E.x + wo.x, E.y + wo.y), cconj(et.twist[k]));
+      const double2 w1 = cmul(make_double2(E.x - wo.x, E.y - wo.y), cconj(et.twist[k + HM]));
+      mreg[2 * u] = round_half_away(w0.x * inv_m);
+      mreg[2 * u + 1] = round_half_away(w0.y * inv_m);
+      mreg[2 * (u + QH)] = round_half_away(w1.x * inv_m);
+      mreg[2 * (u + QH) + 1] = round_half_away(w1.y * inv_m);
     }
   } else {
     constexpr int HM = M / 2;
