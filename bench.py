@@ -126,9 +126,10 @@ def copy_calibration(nbytes=256 << 20, reps=3):
 def encode_flops(n_pts: int, pt_limbs: int, log_n: int) -> float:
     """Algorithmic FP64 operations of encoding n_pts plaintexts of pt_limbs
     limbs each at ring degree 2^log_n (an FMA counts two):
-    * inverse canonical embedding: an FFT of M = N/2 complex points,
-      5 M log2 M, plus the twist by the 2N-th roots (6 M) and the scaling and
-      rounding of the N real coefficients (2 N);
+    * inverse canonical embedding: the M = N/2 point DFT of a real input, as
+      an M/2-point complex FFT (5 (M/2) log2(M/2)) and the split into the
+      M-point spectrum (9 M), plus the twist by the 2N-th roots (6 M) and the
+      scaling and rounding of the N real coefficients (2 N);
     * per limb: reduction of each coefficient modulo q (4 N) and the
       negacyclic NTT, (N/2) log2 N butterflies of 10 operations each -- the
       modular product as an exact double-double product (mul + FMA), a
@@ -136,7 +137,7 @@ def encode_flops(n_pts: int, pt_limbs: int, log_n: int) -> float:
       butterfly's add and subtract."""
     N = 1 << log_n
     M = N // 2
-    fft = 5 * M * (log_n - 1) + 6 * M + 2 * N
+    fft = 5 * (M // 2) * (log_n - 2) + 9 * M + 6 * M + 2 * N
     limb = 4 * N + 10 * (N // 2) * log_n
     return float(n_pts) * (fft + pt_limbs * limb)
 
