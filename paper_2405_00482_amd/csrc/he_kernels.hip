@@ -166,7 +166,7 @@ NTT_KERNEL(LOGN) void k_encrypt_pk(const int64_t* __restrict__ msg, const double
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_decrypt_u64(const double* __restrict__ ct, const double* __restrict__ sk, int lv,
                                      uint64_t* __restrict__ out, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
+  constexpr int N = 1 << LOGN;
   NTT_LDS(LOGN);
   const int i = blockIdx.x;
   const ModQ m = tb.mods[i];
@@ -183,7 +183,7 @@ NTT_KERNEL(LOGN) void k_decrypt_u64(const double* __restrict__ ct, const double*
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_decrypt_f64(const double* __restrict__ ct, const double* const* __restrict__ ct_tab,
                                      const double* __restrict__ sk, int lv, double* __restrict__ out, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
+  constexpr int N = 1 << LOGN;
   NTT_LDS(LOGN);
   const int i = blockIdx.x % (lv + 1), c = blockIdx.x / (lv + 1);
   const ModQ m = tb.mods[i];
@@ -309,7 +309,7 @@ template <int LOGN>
 NTT_KERNEL(LOGN) void k_moddown_q(const double* __restrict__ u, const double* __restrict__ y,
                                    const KsLevel* __restrict__ kl, double* __restrict__ out,
                                    double* const* __restrict__ out_tab, DevTabs tb) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
+  constexpr int N = 1 << LOGN;
   NTT_LDS(LOGN);
   const int alpha = kl->alpha, K = kl->K, lv = kl->lv;
   const int i = blockIdx.x % (lv + 1), x = blockIdx.x / (lv + 1);
