@@ -113,6 +113,32 @@ def ctmat_c4(reps: int = 5) -> dict:
     return out
 
 
+def ntt_throughput(ctx, level: int, polys: int = 1024, reps: int = 5) -> dict:
+    """Forward NTTs alone: `polys` signed-integer polynomials imported into
+    every limb of Q u P at `level` (one limb transform per workgroup: read the
+    8N-byte int64 coefficients, reduce, transform, write 8N bytes).  HIP events,
+    median of reps; algorithmic bytes = 16 N per limb transform."""
+    import torch
+    N = ctx.N
+    limbs = level + 1 + ctx.alpha
+    g = torch.Generator(device="cuda:0").manual_seed(7)
+    m = torch.randint(-(1 << 40), 1 << 40, (polys, N), dtype=torch.int64, device="cuda:0", generator=g)
+    out = torch.empty(polys * limbs * N, dtype=torch.float64, device="cuda:0")
+    ts = []
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.pt_import(level, True, m, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts[1:]))
+    nbytes = 16.0 * N * polys * limbs
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    log(f"[bench] NTT: {polys * limbs} limb transforms at N={N} in {ms:.3f} ms, {gbps:.1f} GB/s algorithmic")
+    return {"limb_transforms": polys * limbs, "ms": ms, "algorithmic_GBps": gbps, "frac_of_hbm_peak": gbps / HBM_PEAK_GBS}
+
+
 def copy_calibration(nbytes=256 << 20, reps=3):
     import torch
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
@@ -343,6 +369,7 @@ def main():
                      "hbm_bytes_per_launch": dk["bytes"] / max(dk["launches"], 1),
                      "avg_launch_us": avg_launch_s * 1e6},
         "roofline_keyswitch": roofline_ks,
+        "ntt": ntt_throughput(ctx, len(d["q"]) - 1),
         "kernels": {k: {"ms_per_step": v["ms_per_step"], "launches_per_step": v["launches"] / args.steps,
                         "algorithmic_GBps": v["bytes"] / max(v["total_ms"] * 1e-3, 1e-12) / 1e9}
                     for k, v in kt.items()},
