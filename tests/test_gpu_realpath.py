@@ -230,3 +230,33 @@ def test_vfl_nn_backward_via_transposed_conversion():
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         print(f"{'forward' if plan is fwd else 'backward'}: rel err 2^{np.log2(err):.2f}")
         assert err < 2.0 ** -20
+
+
+@pytest.mark.parametrize("kind,lazy,o3", [("diag", True, False), ("diag", False, False), ("diag", False, True),
+                                          ("hybrid", False, True), ("row", False, False)])
+def test_c2_full_size_other_plans(kind, lazy, o3):
+    """The logistic-regression gradient at its full size (X^T 256 x 1024 times
+    [[r]], N = 2^13, 3+1 primes) by the diagonal (Eq. 5), GALA-style (O3) and
+    row-wise (Sec. 3.1, 2815 rotations and two rescales) plans: every output
+    within 2^-20 of the FP64 product"""
+    ctx = context("C2")
+    XT, r = W.c2_inputs()
+    m, n = XT.shape
+    k = {"hybrid": 0, "diag": 1, "row": 2}[kind]
+    plan = ctx.plan(k, m, n, lazy=lazy, unhoisted=o3)
+    if kind == "row":
+        assert plan.info["n_rot"] == m * 10 + m - 1
+    sk = ctx.keygen(5)
+    keys = ctx.rotkeys(sk, plan.galois(), 6)
+    pt = dev_f64(plan.bytes("pt") // 8)
+    ct = dev_f64(plan.bytes("ct_in") // 8)
+    out = dev_f64(plan.bytes("ct_out") // 8)
+    y = dev_f64(m)
+    plan.encode_pt(to_dev(XT), pt)
+    plan.encrypt(sk, to_dev(r), 9, ct)
+    plan.matmul(ct, pt, keys, out)
+    plan.decrypt_decode(sk, out, y)
+    ref = XT @ r
+    err = np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"C2 {kind} lazy={lazy} o3={o3}: rel err 2^{np.log2(err):.2f}")
+    assert err < 2.0 ** -20
