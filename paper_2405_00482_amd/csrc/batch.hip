@@ -24,6 +24,8 @@ namespace pvfl {
 // is staged in LDS once and the shifted reads of the loop become LDS reads.
 // Partial sums per (product, chunk) go to part[prod.part0 + i0 / CH].
 // ---------------------------------------------------------------------------
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
 template <int PG, int BETA, int V>
 __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
   extern __shared__ double stage[];  // [PG][BETA + 1][win]
@@ -60,8 +62,8 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
       if (j == BETA && !isq) break;
       const double* src = (j < BETA) ? dig + (size_t)j * KN : pc;
       double* dst = stage + (size_t)(p * (BETA + 1) + j) * win;
-      for (int x = threadIdx.x; x < span; x += 256)
-        dst[x] = src[(t0 & half) | ((t0 + w.i0 + x) & (half - 1))];
+      for (int x = threadIdx.x; x < span; x += 256)  // read once per task: streamed past L2 as well
+        dst[x] = __builtin_nontemporal_load(src + ((t0 & half) | ((t0 + w.i0 + x) & (half - 1))));
     }
   }
   __syncthreads();
@@ -121,10 +123,12 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
         const double* st = stage + (size_t)(p * (BETA + 1)) * win + off;
         double pv[V];
         if (V == 2) {
-          const double2 p2 = *(const double2*)(ptp[p] + (size_t)i * KN);
+          // plaintexts are read once: stream them past L2 so that they do not
+          // evict the key tile the other product groups of this chunk still need
+          const dbl2 p2 = __builtin_nontemporal_load((const dbl2*)(ptp[p] + (size_t)i * KN));
           pv[0] = p2.x; pv[V - 1] = p2.y;
         } else {
-          pv[0] = ptp[p][(size_t)i * KN];
+          pv[0] = __builtin_nontemporal_load(ptp[p] + (size_t)i * KN);
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
