@@ -291,10 +291,13 @@ __device__ __forceinline__ void encode_pt_body(const EncodeArgs& a, int k, const
     double c[PER];
 #pragma unroll
     for (int w = 0; w < PER; ++w) c[w] = w < PH ? mreg[2 * w] : mreg[2 * (w - PH) + 1];
-    // the plaintext buffer is device memory: global stores, which unlike flat
-    // stores do not count against the LDS wait counter of the gather before them
+    // the plaintext buffer is device memory: global stores (unlike flat stores
+    // they do not count against the LDS wait counter of the gather before
+    // them), nontemporal because nothing in this kernel reads them again --
+    // they would only push the twiddle tables and X out of L2
     auto* dst = (__attribute__((address_space(1))) double*)(out_pt + (size_t)l * N);
-    ntt_fwd_regs_out<LOGN>(s, c, tb.fwd_tw + (size_t)pi * N, tb.perm, m, [&](int t, double v) { dst[t] = v; });
+    ntt_fwd_regs_out<LOGN>(s, c, tb.fwd_tw + (size_t)pi * N, tb.perm, m,
+                           [&](int t, double v) { __builtin_nontemporal_store(v, dst + t); });
   }
 }
 
