@@ -162,9 +162,9 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
     if (p >= np || w.i0 >= mp[p]) continue;
     double* part = a.part + (size_t)(a.prods[G.prod[p]].part0 + chunk) * 2 * KN + limbN + t0 + tl;
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      part[v] = reduce(acc0[p][v], m);
-      part[KN + v] = reduce(acc1[p][v], m);
+    for (int v = 0; v < V; ++v) {  // summed by a later launch: keep them out of L2
+      __builtin_nontemporal_store(reduce(acc0[p][v], m), part + v);
+      __builtin_nontemporal_store(reduce(acc1[p][v], m), part + KN + v);
     }
   }
 }
