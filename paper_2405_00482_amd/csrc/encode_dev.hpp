@@ -200,10 +200,20 @@ __device__ __forceinline__ void encode_to_regs_v(Gather gather, double2* z, doub
     // The half transform runs on the first half of the threads with every
     // other twiddle of the M-point table.
     constexpr int HM = M / 2, QH = HM / T;  // QH = 4 complex inputs per thread
+    // The thread gathers slots j = tid + u T; slot j is DFT input f = (5^j
+    // mod 2N - 1) / 4, i.e. component f mod 2 of y[f / 2].
     double v[2 * QH];
-    gather([&](int u) { return (int)et.f2slot[2 * (tid + (u >> 1) * T) + (u & 1)]; }, v);
+    gather([&](int u) { return tid + u * T; }, v);
+    {
+      OrbitWalk ow = OrbitWalk::start<LOGN>();
+      double* zd = (double*)z;
 #pragma unroll
-    for (int u = 0; u < QH; ++u) z[cpad(tid + u * T)] = make_double2(v[2 * u], v[2 * u + 1]);
+      for (int u = 0; u < 2 * QH; ++u) {
+        const int f = (int)(ow.e >> 2);
+        zd[2 * cpad(f >> 1) + (f & 1)] = v[u];
+        ow.next<LOGN>();
+      }
+    }
     __syncthreads();
     fft_passes<LOGN - 1, 0, 1>(z, et.fft_tw, false);
 #pragma unroll

@@ -47,15 +47,4 @@ __device__ __forceinline__ int orbit_shift(int t, int rot, int half) {
   return (t & half) | ((t + rot) & (half - 1));
 }
 
-// ---------------------------------------------------------------------------
-// LDS staging helpers
-// ---------------------------------------------------------------------------
-// after ntt_fwd*: write the bit-reversed LDS result out in orbit order
-template <int LOGN>
-__device__ __forceinline__ void store_orbit(const double* s, double* __restrict__ out, const uint32_t* __restrict__ perm) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  for (int t = threadIdx.x; t < N; t += T) out[t] = s[lds_pad(perm[t])];
-}
-
-
 }  // namespace pvfl

@@ -12,9 +12,13 @@
 //
 // Schedule.  N/16 threads each hold 16 elements in registers; up to four
 // radix-2 stages run on them between two LDS exchanges ("passes"), so a 2^14
-// transform makes four LDS round trips instead of fourteen.  The LDS array is
-// padded by one double every 16 (lds_pad) so that the strided set loads of
-// every pass are close to bank-conflict free.
+// transform makes four LDS round trips instead of fourteen.  In the forward
+// transform only the first exchange crosses waves; the later passes stay
+// inside one wave's 1024 elements and need no workgroup barrier (see
+// ntt_fwd_regs).  The LDS array is padded by one double every 16 (lds_pad)
+// so that the strided set loads of every pass are close to bank-conflict
+// free.  The orbit-order permutation is computed from powers of 5 (OrbitWalk)
+// rather than read from a table, up to N = 2^14.
 //
 // Value ranges (q < 2^48): inputs may be any integers with |x| < 2^51.  A
 // twiddle mulmod of |a| <= 2^51 by a centred twiddle returns |r| <= 0.875 q
@@ -25,6 +29,8 @@
 // Outputs are centred.
 #pragma once
 #include "fp64_mod.hpp"
+
+#include <type_traits>
 
 namespace pvfl {
 
@@ -47,7 +53,7 @@ struct NttShape {
   static constexpr int T = (1 << LOGH) / 16;    // threads per workgroup
   static constexpr int PER = N / T;             // coefficients per thread: 16, or 32 at 2^15
   static constexpr int LDS = (1 << LOGH) + (1 << LOGH) / 16;  // padded LDS doubles
-  static constexpr int S0 = LOGH - 12;          // stages of the leading (large-span) pass
+  static constexpr int S0 = LOGH - 12;          // stages of the inverse's last (large-span) pass
 };
 
 __device__ __forceinline__ int lds_pad(int j) { return j + (j >> 4); }
@@ -135,50 +141,99 @@ __device__ __forceinline__ void recentre(double (&x)[N], ModQ m) {
   for (int k = 0; k < N; ++k) x[k] = reduce(x[k], m);
 }
 
-// Forward transform.  c[w] is coefficient tid + w*T of the thread (natural
-// order, any |x| < 2^51); the first pass runs on these registers directly.
+// Sets with a compile-time span 2^LS: element u of a set lies at padded
+// offset (u << LS) + ((u << LS) >> 4) from the set's base.  This holds when
+// the base is below 2^LS modulo 2^(LS+4) (then adding u 2^LS never carries
+// into a new run of 16 except through the multiple-of-16 part), which every
+// pass of the forward transform guarantees.
+template <int S, int LS, int NQ>
+__device__ __forceinline__ void lds_load_c(const double* s, double (&x)[16], const int (&base)[NQ]) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double* p = s + lds_pad(base[q]);
+#pragma unroll
+    for (int u = 0; u < (1 << S); ++u) x[q * (1 << S) + u] = p[(u << LS) + ((u << LS) >> 4)];
+  }
+}
+template <int S, int LS, int NQ>
+__device__ __forceinline__ void lds_store_c(double* s, const double (&x)[16], const int (&base)[NQ]) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double* p = s + lds_pad(base[q]);
+#pragma unroll
+    for (int u = 0; u < (1 << S); ++u) p[(u << LS) + ((u << LS) >> 4)] = x[q * (1 << S) + u];
+  }
+}
+
+// Orders a wave's LDS stores before its later LDS loads of what other lanes
+// of the same wave stored (LDS operations of one wave execute in order; the
+// fences keep the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Forward transform (2^12 <= N <= 2^14, N/16 threads).  c[w] is coefficient
+// tid + w*T of the thread (natural order, any |x| < 2^51).  Schedule:
+//  * stages 0..3 (spans N/2 .. N/16) on the thread's own 16 coefficients,
+//    which form one radix-16 set, in registers;
+//  * one exchange through LDS behind a workgroup barrier, after which wave
+//    w owns the 1024 consecutive elements [1024 w, 1024 w + 1024);
+//  * stages 4..7 and 8..11 as radix-16 sets, and the last LOGN - 12 stages
+//    as sets of consecutive elements, all inside the wave's own 1024
+//    elements: these exchanges go through the wave's part of LDS with no
+//    workgroup barrier, so the waves drift apart and one wave's LDS traffic
+//    overlaps another's arithmetic.
+// Re-centring after stage 7 and at the end (at most 8 stages between two).
 // The result is left in LDS in bit-reversed order, centred: read it with
-// s[lds_pad(perm[t])] after the call (which ends with a barrier).  The call
-// begins with a barrier, so `s` may still be in use by the caller before it.
-// Re-centring: at the end of a pass when the next pass would take the count
-// of stages since the last re-centring past 9, and after the last pass.  Each
-// pass's twiddles are loaded before the barrier that precedes it, so their
-// latency overlaps the LDS exchange.
+// s[lds_pad(j)] after the call (which ends with a barrier).  The call begins
+// with a barrier, so `s` may still be in use by the caller before it.
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd_regs(double* s, const double (&c)[16], const double* __restrict__ tw, ModQ m) {
-  constexpr int S0 = NttShape<LOGN>::S0;
-  constexpr int S = S0 > 0 ? S0 : 4;
+  static_assert(LOGN >= 12 && LOGN <= 14, "one wave owns 1024 elements of an LDS-resident limb");
   double x[16];
-  int since = S == 4 ? 0 : S;  // stages since the last re-centring
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) x[u] = reduce(c[u], m);
   {
-    int base[16 >> S];
-    pass_bases<LOGN, S>(base, LOGN - S);
-    // register slot (q, u) holds coefficient base[q] + u*2^(LOGN-S) = tid + T*(q + u*(16>>S))
-#pragma unroll
-    for (int q = 0; q < (16 >> S); ++q)
-#pragma unroll
-      for (int u = 0; u < (1 << S); ++u) x[q * (1 << S) + u] = reduce(c[q + u * (16 >> S)], m);
-    ct_pass_regs<LOGN, S>(x, 0, base, tw, m);
-    if (S == 4) recentre(x, m);
+    const int base[1] = {tid};
+    ct_pass_regs<LOGN, 4>(x, 0, base, tw, m);
     __syncthreads();
-    lds_store_sets<S>(s, x, base, LOGN - S);
+    lds_store_c<4, LOGN - 4>(s, x, base);
   }
   __syncthreads();
-#pragma unroll 1
-  for (int lg = S; lg < LOGN; lg += 4) {
-    const int ls = LOGN - lg - 4;
+  {  // stages 4..7: sets {base + u 2^(LOGN-8)} inside the wave's 1024 elements
+    constexpr int LS = LOGN - 8;
     int base[1];
-    pass_bases<LOGN, 4>(base, ls);
-    lds_load_sets<4>(s, x, base, ls);
-    ct_pass_regs<LOGN, 4>(x, lg, base, tw, m);
-    since += 4;
-    if (lg + 4 >= LOGN || since + 4 > 9) {
-      recentre(x, m);
-      since = 0;
-    }
-    lds_store_sets<4>(s, x, base, ls);
-    __syncthreads();
+    pass_bases<LOGN, 4>(base, LS);
+    lds_load_c<4, LS>(s, x, base);
+    ct_pass_regs<LOGN, 4>(x, 4, base, tw, m);
+    recentre(x, m);
+    lds_store_c<4, LS>(s, x, base);
   }
+  wave_lds_sync();
+  {  // stages 8..11
+    constexpr int LS = LOGN - 12;
+    int base[1];
+    pass_bases<LOGN, 4>(base, LS);
+    lds_load_c<4, LS>(s, x, base);
+    ct_pass_regs<LOGN, 4>(x, 8, base, tw, m);
+    if constexpr (LOGN == 12) recentre(x, m);
+    lds_store_c<4, LS>(s, x, base);
+  }
+  if constexpr (LOGN > 12) {  // stages 12 .. LOGN-1: sets of 2^S consecutive elements, 16 per thread
+    constexpr int S = LOGN - 12, NQ = 16 >> S;
+    wave_lds_sync();
+    int base[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) base[q] = 16 * tid + (q << S);
+    lds_load_c<S, 0>(s, x, base);
+    ct_pass_regs<LOGN, S>(x, 12, base, tw, m);
+    recentre(x, m);
+    lds_store_c<S, 0>(s, x, base);
+  }
+  __syncthreads();
 }
 
 // forward transform of coefficients produced by load(j)
@@ -272,15 +327,38 @@ __device__ __forceinline__ void ntt_inv(double* s, Store store, const double* __
 }
 
 
-// Bring an evaluation-domain limb (orbit order, |x| <= 2^51) into LDS in
-// bit-reversed order for the inverse transform.
+// Orbit order <-> bit-reversed index, computed instead of read from the
+// table (2^12 <= N <= 2^14).  Slot t < N/2 holds the exponent e = 5^t mod 2N,
+// at bit-reversed index brv((e - 1) / 2); slot t + N/2 holds -e, at the
+// complement (N - 1) - brv((e - 1) / 2).  A thread's slots t = tid + w N/16
+// have e = 5^tid (5^(N/16))^w: as 2N is a power of two every product is
+// exact in 32 bits and the reduction is a mask.
 template <int LOGN>
-__device__ __forceinline__ void lds_from_orbit(double* s, const double* __restrict__ in, const uint32_t* __restrict__ perm,
-                                               ModQ m) {
-  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
-  for (int t = threadIdx.x; t < N; t += T) s[lds_pad(perm[t])] = reduce(in[t], m);
-  __syncthreads();
+constexpr uint32_t pow5_step() {  // 5^(N/16) mod 2N
+  uint32_t r = 1;
+  for (int i = 0; i < (1 << LOGN) / 16; ++i) r = (r * 5u) & ((2u << LOGN) - 1u);
+  return r;
 }
+struct OrbitWalk {
+  uint32_t e;  // 5^(tid + w N/16) mod 2N for the thread's current w
+  template <int LOGN>
+  __device__ __forceinline__ static OrbitWalk start() {  // 5^tid mod 2N, tid < N/16
+    const uint32_t mask = (2u << LOGN) - 1u, tid = threadIdx.x;
+    uint32_t r = 1, b = 5;
+#pragma unroll
+    for (int k = 0; k < LOGN - 4; ++k) {
+      if ((tid >> k) & 1u) r = (r * b) & mask;
+      b = (b * b) & mask;
+    }
+    return OrbitWalk{r};
+  }
+  template <int LOGN>
+  __device__ __forceinline__ int brv_index() const { return (int)(__brev(e >> 1) >> (32 - LOGN)); }
+  template <int LOGN>
+  __device__ __forceinline__ void next() {
+    e = (e * std::integral_constant<uint32_t, pow5_step<LOGN>()>::value) & ((2u << LOGN) - 1u);
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Size-generic entry points.  Thread tid owns coefficients j = tid + w*T,
@@ -304,15 +382,27 @@ __device__ __forceinline__ void ntt_fwd_regs_out(double* s, const double (&c)[Nt
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
   if constexpr (LOGN <= 14) {
     ntt_fwd_regs<LOGN>(s, c, tw, m);
-    // groups of OU slots: their permutation entries are loaded together
-    constexpr int OU = 4;
+    // slots t and t + N/2 for two w at a time: four LDS reads in flight
+    OrbitWalk ow = OrbitWalk::start<LOGN>();
 #pragma unroll 1
-    for (int t0 = threadIdx.x; t0 < N; t0 += OU * T) {
-      uint32_t pe[OU];
+    for (int w = 0; w < 8; w += 2) {
+      int j[2];
 #pragma unroll
-      for (int u = 0; u < OU; ++u) pe[u] = perm[t0 + u * T];
+      for (int h = 0; h < 2; ++h) {
+        j[h] = ow.brv_index<LOGN>();
+        ow.next<LOGN>();
+      }
+      double v[4];
 #pragma unroll
-      for (int u = 0; u < OU; ++u) out(t0 + u * T, s[lds_pad(pe[u])]);
+      for (int h = 0; h < 2; ++h) {
+        v[2 * h] = s[lds_pad(j[h])];
+        v[2 * h + 1] = s[lds_pad(j[h] ^ (N - 1))];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        out((int)threadIdx.x + (w + h) * T, v[2 * h]);
+        out((int)threadIdx.x + (w + h) * T + N / 2, v[2 * h + 1]);
+      }
     }
   } else {
     constexpr int H = 1 << 14;
@@ -351,7 +441,14 @@ __device__ __forceinline__ void ntt_inv_in_regs(double* s, In in, const double* 
                                                 double (&c)[NttShape<LOGN>::PER]) {
   constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
   if constexpr (LOGN <= 14) {
-    for (int t = threadIdx.x; t < N; t += T) s[lds_pad(perm[t])] = reduce(in(t), m);
+    OrbitWalk ow = OrbitWalk::start<LOGN>();
+#pragma unroll 2
+    for (int w = 0; w < 8; ++w) {
+      const int t = (int)threadIdx.x + w * T, j = ow.brv_index<LOGN>();
+      s[lds_pad(j)] = reduce(in(t), m);
+      s[lds_pad(j ^ (N - 1))] = reduce(in(t + N / 2), m);
+      ow.next<LOGN>();
+    }
     __syncthreads();
     ntt_inv_regs<LOGN>(s, c, itw, m, ninv);
   } else {
