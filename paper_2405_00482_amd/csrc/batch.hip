@@ -86,66 +86,85 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
 #pragma unroll
     for (int v = 0; v < V; ++v) acc0[p][v] = acc1[p][v] = 0.0;
   int cnt = 0;
-  for (int i = w.i0; i < w.i1; ++i) {
-    const int off = tl + (i - w.i0);  // window index of this thread's first element
-    if (i == 0) {
-      if (isq) {
-#pragma unroll
-        for (int p = 0; p < PG; ++p) {
-          if (p >= np) continue;
-          const double* pcs = stage + (size_t)(p * (BETA + 1) + BETA) * win;
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            const double pv = ptp[p][v];
-            acc0[p][v] += mulmod(pv, pcs[off + v], m);
-            acc1[p][v] += mulmod(pv, a.pc[(size_t)G.prod[p] * a.pc_stride + Qoff + limbN + t0 + tl + v], m);
-          }
-        }
-      }
-    } else {
-      const double* key = a.keys + (size_t)a.slot_of_rot[i] * a.key_stride + (size_t)klimb * N + t0 + tl;
-      double kb[BETA][V], ka[BETA][V];
-#pragma unroll
-      for (int j = 0; j < BETA; ++j) {
-        if (V == 2) {
-          const double2 b2 = *(const double2*)(key + (size_t)j * 2 * a.key_limbs * N);
-          const double2 a2 = *(const double2*)(key + (size_t)(j * 2 + 1) * a.key_limbs * N);
-          kb[j][0] = b2.x; kb[j][V - 1] = b2.y;
-          ka[j][0] = a2.x; ka[j][V - 1] = a2.y;
-        } else {
-          kb[j][0] = key[(size_t)j * 2 * a.key_limbs * N];
-          ka[j][0] = key[(size_t)(j * 2 + 1) * a.key_limbs * N];
-        }
-      }
+  int i = w.i0;
+  if (i == 0) {  // diagonal 0: no rotation; P c0 on the Q limbs
+    if (isq) {
 #pragma unroll
       for (int p = 0; p < PG; ++p) {
-        if (p >= np || i >= mp[p]) continue;
-        const double* st = stage + (size_t)(p * (BETA + 1)) * win + off;
-        double pv[V];
-        if (V == 2) {
-          // plaintexts are read once: stream them past L2 so that they do not
-          // evict the key tile the other product groups of this chunk still need
-          const dbl2 p2 = __builtin_nontemporal_load((const dbl2*)(ptp[p] + (size_t)i * KN));
-          pv[0] = p2.x; pv[V - 1] = p2.y;
-        } else {
-          pv[0] = __builtin_nontemporal_load(ptp[p] + (size_t)i * KN);
-        }
+        if (p >= np) continue;
+        const double* pcs = stage + (size_t)(p * (BETA + 1) + BETA) * win + tl;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          double u0 = 0.0, u1 = 0.0;
-#pragma unroll
-          for (int j = 0; j < BETA; ++j) {
-            const double d = st[(size_t)j * win + v];
-            u0 += mulmod(d, kb[j][v], m);
-            u1 += mulmod(d, ka[j][v], m);
-          }
-          if (isq) u0 += st[(size_t)BETA * win + v];
-          acc0[p][v] += mulmod(pv[v], u0, m);
-          acc1[p][v] += mulmod(pv[v], u1, m);
+          const double pv = ptp[p][v];
+          acc0[p][v] += mulmod(pv, pcs[v], m);
+          acc1[p][v] += mulmod(pv, a.pc[(size_t)G.prod[p] * a.pc_stride + Qoff + limbN + t0 + tl + v], m);
         }
       }
     }
-    if (++cnt == 8) {
+    ++i;
+    ++cnt;
+  }
+  // key limbs (b_j, a_j) of rotation i at this thread's V indices
+  auto load_keys = [&](int ii, double (&kb)[BETA][V], double (&ka)[BETA][V]) {
+    const double* key = a.keys + (size_t)a.slot_of_rot[ii] * a.key_stride + (size_t)klimb * N + t0 + tl;
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) {
+      if (V == 2) {
+        const double2 b2 = *(const double2*)(key + (size_t)j * 2 * a.key_limbs * N);
+        const double2 a2 = *(const double2*)(key + (size_t)(j * 2 + 1) * a.key_limbs * N);
+        kb[j][0] = b2.x; kb[j][V - 1] = b2.y;
+        ka[j][0] = a2.x; ka[j][V - 1] = a2.y;
+      } else {
+        kb[j][0] = key[(size_t)j * 2 * a.key_limbs * N];
+        ka[j][0] = key[(size_t)(j * 2 + 1) * a.key_limbs * N];
+      }
+    }
+  };
+  // plaintext values of diagonal i for every product of the group.  A
+  // product without diagonal i (or an empty group slot) reads a row it has
+  // and contributes zero, so the loads are unconditional and the two
+  // diagonals' loads below can all be in flight together.  Plaintexts are
+  // read once: stream them past L2 so that they do not evict the key tile
+  // the other product groups of this chunk still need.
+  auto load_pt = [&](int ii, double (&pv)[PG][V]) {
+#pragma unroll
+    for (int p = 0; p < PG; ++p) {
+      const bool has = p < np && ii < mp[p];
+      const double* src = ptp[p < np ? p : 0] + (size_t)(has ? ii : 0) * KN;
+      if (V == 2) {
+        const dbl2 p2 = __builtin_nontemporal_load((const dbl2*)src);
+        pv[p][0] = has ? p2.x : 0.0;
+        pv[p][V - 1] = has ? p2.y : 0.0;
+      } else {
+        const double x = __builtin_nontemporal_load(src);
+        pv[p][0] = has ? x : 0.0;
+      }
+    }
+  };
+  auto apply = [&](int ii, const double (&kb)[BETA][V], const double (&ka)[BETA][V], const double (&pv)[PG][V]) {
+    const int off = tl + (ii - w.i0);  // window index of this thread's first element
+#pragma unroll
+    for (int p = 0; p < PG; ++p) {
+      const double* st = stage + (size_t)(p * (BETA + 1)) * win + off;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        double u0 = 0.0, u1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < BETA; ++j) {
+          const double d = st[(size_t)j * win + v];
+          u0 += mulmod(d, kb[j][v], m);
+          u1 += mulmod(d, ka[j][v], m);
+        }
+        if (isq) u0 += st[(size_t)BETA * win + v];
+        acc0[p][v] += mulmod(pv[p][v], u0, m);
+        acc1[p][v] += mulmod(pv[p][v], u1, m);
+      }
+    }
+  };
+  // re-centre after 8 (9 in the chunk holding diagonal 0) terms of |r| < q:
+  // |acc| < 9.5 q < 2^52, the range reduce() takes
+  auto settle = [&]() {
+    if (cnt >= 8) {
 #pragma unroll
       for (int p = 0; p < PG; ++p)
 #pragma unroll
@@ -155,6 +174,27 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
         }
       cnt = 0;
     }
+  };
+  // two diagonals per step: both diagonals' key and plaintext loads are
+  // issued before either is used, which doubles the memory requests each
+  // wave has in flight (the LDS stage already limits occupancy to three
+  // waves per SIMD, which leaves the registers for this)
+  for (; i + 1 < w.i1; i += 2) {
+    double kb0[BETA][V], ka0[BETA][V], kb1[BETA][V], ka1[BETA][V], pv0[PG][V], pv1[PG][V];
+    load_keys(i, kb0, ka0);
+    load_pt(i, pv0);
+    load_keys(i + 1, kb1, ka1);
+    load_pt(i + 1, pv1);
+    apply(i, kb0, ka0, pv0);
+    apply(i + 1, kb1, ka1, pv1);
+    cnt += 2;
+    settle();
+  }
+  if (i < w.i1) {
+    double kb0[BETA][V], ka0[BETA][V], pv0[PG][V];
+    load_keys(i, kb0, ka0);
+    load_pt(i, pv0);
+    apply(i, kb0, ka0, pv0);
   }
   const int chunk = w.i0 / a.CH;
 #pragma unroll
