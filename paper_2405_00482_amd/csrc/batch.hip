@@ -49,7 +49,13 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
   const bool isq = r <= a.lv;
   const ModQ m = a.mods[pi];
   const int np = G.np;
-  const int win = TILE + a.CH;
+  // Staged row layout.  With V = 2 a thread reads elements 2 tid + s and
+  // 2 tid + s + 1: stride 2 across the wave, two lanes on every LDS bank.
+  // The rows hold even and odd elements in separate halves instead (element
+  // x at (x & 1) hw + x / 2), so every read of the loop is stride 1.
+  const int hw = (TILE + a.CH + 1) / 2;
+  const int win = V == 2 ? 2 * hw : TILE + a.CH;  // row stride (doubles)
+  auto spos = [&](int x) { return V == 2 ? (x & 1) * hw + (x >> 1) : x; };
   const int span = TILE + (w.i1 - w.i0);
   const size_t KN = (size_t)K * N;
   const size_t Qoff = (size_t)(a.lv + 1) * N;
@@ -63,7 +69,7 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
       const double* src = (j < BETA) ? dig + (size_t)j * KN : pc;
       double* dst = stage + (size_t)(p * (BETA + 1) + j) * win;
       for (int x = threadIdx.x; x < span; x += 256)  // read once per task: streamed past L2 as well
-        dst[x] = __builtin_nontemporal_load(src + ((t0 & half) | ((t0 + w.i0 + x) & (half - 1))));
+        dst[spos(x)] = __builtin_nontemporal_load(src + ((t0 & half) | ((t0 + w.i0 + x) & (half - 1))));
     }
   }
   __syncthreads();
@@ -92,11 +98,11 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
 #pragma unroll
       for (int p = 0; p < PG; ++p) {
         if (p >= np) continue;
-        const double* pcs = stage + (size_t)(p * (BETA + 1) + BETA) * win + tl;
+        const double* pcs = stage + (size_t)(p * (BETA + 1) + BETA) * win;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           const double pv = ptp[p][v];
-          acc0[p][v] += mulmod(pv, pcs[v], m);
+          acc0[p][v] += mulmod(pv, pcs[spos(tl + v)], m);
           acc1[p][v] += mulmod(pv, a.pc[(size_t)G.prod[p] * a.pc_stride + Qoff + limbN + t0 + tl + v], m);
         }
       }
@@ -142,20 +148,22 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
     }
   };
   auto apply = [&](int ii, const double (&kb)[BETA][V], const double (&ka)[BETA][V], const double (&pv)[PG][V]) {
-    const int off = tl + (ii - w.i0);  // window index of this thread's first element
+    const int sh = ii - w.i0;  // shift of diagonal ii inside the window
 #pragma unroll
     for (int p = 0; p < PG; ++p) {
-      const double* st = stage + (size_t)(p * (BETA + 1)) * win + off;
+      const double* st = stage + (size_t)(p * (BETA + 1)) * win;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
+        // spos(tl + sh + v), written out with tl = 2 tid for V = 2
+        const int pos = V == 2 ? ((sh + v) & 1) * hw + (int)threadIdx.x + ((sh + v) >> 1) : tl + sh + v;
         double u0 = 0.0, u1 = 0.0;
 #pragma unroll
         for (int j = 0; j < BETA; ++j) {
-          const double d = st[(size_t)j * win + v];
+          const double d = st[(size_t)j * win + pos];
           u0 += mulmod(d, kb[j][v], m);
           u1 += mulmod(d, ka[j][v], m);
         }
-        if (isq) u0 += st[(size_t)BETA * win + v];
+        if (isq) u0 += st[(size_t)BETA * win + pos];
         acc0[p][v] += mulmod(pv[p][v], u0, m);
         acc1[p][v] += mulmod(pv[p][v], u1, m);
       }
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(256) void k_readout_batch(const double* __restrict_
 template <int PG, int V>
 static hipError_t diag_batch_pgv(const LaunchCtx& L, const BatchDiagArgs& a, int beta) {
   const dim3 grid(8 * a.per_xcd);
-  const size_t lds = sizeof(double) * (size_t)PG * (beta + 1) * (256 * V + a.CH);
+  const size_t lds = sizeof(double) * (size_t)PG * (beta + 1) * (256 * V + a.CH + 1);  // row stride <= win + 1
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   switch (beta) {
     case 1: hipLaunchKernelGGL((k_diag_batch<PG, 1, V>), grid, dim3(256), lds, L.stream, a); break;
