@@ -37,7 +37,7 @@ __device__ __forceinline__ void fft_pass(double2* a, const double2* __restrict__
   static_assert(M == 8 * T, "eight FFT points per thread");
   constexpr int LS = LOGM - S0 - S;  // log2 stride
   constexpr unsigned stride = 1u << LS;
-  const unsigned tid = threadIdx.x;
+  const unsigned tid = opaque_tid();
   if (tid < (unsigned)T) {  // a transform of M < 8 * blockDim points leaves the other threads idle
   int base[NS], off[NS];
   double2 x[8];
@@ -182,6 +182,47 @@ __device__ __forceinline__ void gather_slots(const EncodeArgs& a, int k, double 
   }
 }
 
+// The slot values v[u] of slots j = tid + u T (u < 8, N <= 2^14) -> FFT ->
+// rounded coefficients in registers, as encode_to_regs_v describes.  Slot j
+// is DFT input f = (5^j mod 2N - 1) / 4, i.e. component f mod 2 of y[f / 2].
+// Begins by writing LDS (barrier before the call if LDS is in use); ends
+// with a barrier.
+template <int LOGN>
+__device__ __forceinline__ void fft_split_regs(const double (&v)[8], double2* z, double* mreg, const EncTabs& et) {
+  static_assert(LOGN <= 14, "the 2^15 ring's encoder splits its FFT in halves");
+  constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T, HM = M / 2, QH = HM / T;
+  const int tid = opaque_tid();
+  const double inv_m = 1.0 / (double)M;
+  {
+    OrbitWalk ow = OrbitWalk::start<LOGN>();
+    double* zd = (double*)z;
+#pragma unroll
+    for (int u = 0; u < 2 * QH; ++u) {
+      const int f = (int)(ow.e >> 2);
+      zd[2 * cpad(f >> 1) + (f & 1)] = v[u];
+      ow.next<LOGN>();
+    }
+  }
+  __syncthreads();
+  fft_passes<LOGN - 1, 0, 1>(z, et.fft_tw, false);
+#pragma unroll
+  for (int u = 0; u < QH; ++u) {
+    const int k = tid + u * T;
+    const double2 Yk = z[cpad(brev(k, LOGN - 2))];
+    const double2 Yc = z[cpad(brev((HM - k) & (HM - 1), LOGN - 2))];
+    const double2 E = make_double2(0.5 * (Yk.x + Yc.x), 0.5 * (Yk.y - Yc.y));
+    const double2 O = make_double2(0.5 * (Yk.y + Yc.y), -0.5 * (Yk.x - Yc.x));
+    const double2 wo = cmul(O, et.fft_tw[k]);
+    const double2 w0 = cmul(make_double2(E.x + wo.x, E.y + wo.y), cconj(et.twist[k]));
+    const double2 w1 = cmul(make_double2(E.x - wo.x, E.y - wo.y), cconj(et.twist[k + HM]));
+    mreg[2 * u] = round_half_away(w0.x * inv_m);
+    mreg[2 * u + 1] = round_half_away(w0.y * inv_m);
+    mreg[2 * (u + QH)] = round_half_away(w1.x * inv_m);
+    mreg[2 * (u + QH) + 1] = round_half_away(w1.y * inv_m);
+  }
+  __syncthreads();
+}
+
 // slots -> FFT -> rounded coefficients in registers: mreg[2u] = m_k and
 // mreg[2u+1] = m_(k+N/2) for k = tid + u T, u < M/T.  gather(slot_of, v)
 // fills v[u] with the scaled value of slot slot_of(u) for every u of v.  At N = 2^15 the first DIF stage (pairs i, i + M/2, owned
@@ -189,9 +230,8 @@ __device__ __forceinline__ void gather_slots(const EncodeArgs& a, int k, double 
 // other; half h yields the coefficients with k = h mod 2.
 template <int LOGN, class Gather>
 __device__ __forceinline__ void encode_to_regs_v(Gather gather, double2* z, double* mreg, const EncTabs& et) {
-  constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T, PH = M / T;
-  const int tid = threadIdx.x;
-  const double inv_m = 1.0 / (double)M;
+  constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T;
+  const int tid = opaque_tid();
   if constexpr (LOGN <= 14) {
     // The DFT input x[f] (slot value at f = f_j) is real: pack y[n] = x[2n] +
     // i x[2n+1], transform M/2 points, and split (real-input FFT):
@@ -200,39 +240,12 @@ __device__ __forceinline__ void encode_to_regs_v(Gather gather, double2* z, doub
     // The half transform runs on the first half of the threads with every
     // other twiddle of the M-point table.
     constexpr int HM = M / 2, QH = HM / T;  // QH = 4 complex inputs per thread
-    // The thread gathers slots j = tid + u T; slot j is DFT input f = (5^j
-    // mod 2N - 1) / 4, i.e. component f mod 2 of y[f / 2].
     double v[2 * QH];
     gather([&](int u) { return tid + u * T; }, v);
-    {
-      OrbitWalk ow = OrbitWalk::start<LOGN>();
-      double* zd = (double*)z;
-#pragma unroll
-      for (int u = 0; u < 2 * QH; ++u) {
-        const int f = (int)(ow.e >> 2);
-        zd[2 * cpad(f >> 1) + (f & 1)] = v[u];
-        ow.next<LOGN>();
-      }
-    }
-    __syncthreads();
-    fft_passes<LOGN - 1, 0, 1>(z, et.fft_tw, false);
-#pragma unroll
-    for (int u = 0; u < QH; ++u) {
-      const int k = tid + u * T;
-      const double2 Yk = z[cpad(brev(k, LOGN - 2))];
-      const double2 Yc = z[cpad(brev((HM - k) & (HM - 1), LOGN - 2))];
-      const double2 E = make_double2(0.5 * (Yk.x + Yc.x), 0.5 * (Yk.y - Yc.y));
-      const double2 O = make_double2(0.5 * (Yk.y + Yc.y), -0.5 * (Yk.x - Yc.x));
-      const double2 wo = cmul(O, et.fft_tw[k]);
-      const double2 w0 = cmul(make_double2(E.x + wo.x, E.y + wo.y), cconj(et.twist[k]));
-      const double2 w1 = cmul(make_double2(E.x - wo.x, E.y - wo.y), cconj(et.twist[k + HM]));
-      mreg[2 * u] = round_half_away(w0.x * inv_m);
-      mreg[2 * u + 1] = round_half_away(w0.y * inv_m);
-      mreg[2 * (u + QH)] = round_half_away(w1.x * inv_m);
-      mreg[2 * (u + QH) + 1] = round_half_away(w1.y * inv_m);
-    }
+    fft_split_regs<LOGN>(v, z, mreg, et);
   } else {
-    constexpr int HM = M / 2;
+    constexpr int HM = M / 2, PH = M / T;
+    const double inv_m = 1.0 / (double)M;
     double2 v0[HM / T];
 #pragma unroll
     for (int u = 0; u < HM / T; ++u) {
@@ -262,8 +275,8 @@ __device__ __forceinline__ void encode_to_regs_v(Gather gather, double2* z, doub
         }
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 template <int LOGN, bool CT>

@@ -1,6 +1,11 @@
 // HIP kernels of the RNS-CKKS ciphertext x plaintext matrix product for gfx950.
 // Residues are exact binary64 integers (fp64_mod.hpp); evaluation-domain limbs
 // are stored in the orbit order of ntt_core.hpp.
+// Key generation, encryption and the key-switching kernels loop over limbs
+// in registers: keep their thread-index arithmetic inside the loops (see
+// opaque_tid in ntt_core.hpp).
+#define PVFL_OPAQUE_TID 1
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

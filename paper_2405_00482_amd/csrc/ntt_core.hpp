@@ -58,6 +58,21 @@ struct NttShape {
 
 __device__ __forceinline__ int lds_pad(int j) { return j + (j >> 4); }
 
+// The thread index.  A source file that defines PVFL_OPAQUE_TID before
+// including this header gets it hidden from loop-invariant code motion (the
+// empty asm statement may change it as far as the compiler knows): its
+// kernels loop over many limbs, and would otherwise hoist every index and
+// address computed from the thread index out of the loop and keep them all
+// live in registers at once, which spills.  Elsewhere the compiler keeps
+// those values, which saves recomputing them.
+static __device__ __forceinline__ int opaque_tid() {
+  unsigned t = threadIdx.x;
+#if defined(PVFL_OPAQUE_TID)
+  asm volatile("" : "+v"(t));
+#endif
+  return (int)t;
+}
+
 // Pass geometry.  A pass of S radix-2 stages works on register sets of 2^S
 // elements {base + u * 2^ls} (2^ls = span of the pass's last stage); thread
 // tid owns sets c = q*T + tid, q < 16 / 2^S, with base = blk * 2^(ls+S) + off,
@@ -69,7 +84,7 @@ __device__ __forceinline__ void pass_bases(int (&base)[16 >> S], int ls) {
   constexpr int T = NttShape<LOGN>::T;
 #pragma unroll
   for (int q = 0; q < (16 >> S); ++q) {
-    const unsigned c = (unsigned)(q * T) + threadIdx.x;
+    const unsigned c = (unsigned)(q * T) + opaque_tid();
     base[q] = (int)(((c >> ls) << (ls + S)) | (c & ((1u << ls) - 1u)));
   }
 }
@@ -193,7 +208,7 @@ template <int LOGN>
 __device__ __forceinline__ void ntt_fwd_regs(double* s, const double (&c)[16], const double* __restrict__ tw, ModQ m) {
   static_assert(LOGN >= 12 && LOGN <= 14, "one wave owns 1024 elements of an LDS-resident limb");
   double x[16];
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
 #pragma unroll
   for (int u = 0; u < 16; ++u) x[u] = reduce(c[u], m);
   {
@@ -242,7 +257,7 @@ __device__ __forceinline__ void ntt_fwd(double* s, Load load, const double* __re
   constexpr int T = NttShape<LOGN>::T;
   double c[16];
 #pragma unroll
-  for (int w = 0; w < 16; ++w) c[w] = load((int)threadIdx.x + w * T);
+  for (int w = 0; w < 16; ++w) c[w] = load((int)opaque_tid() + w * T);
   ntt_fwd_regs<LOGN>(s, c, tw, m);
 }
 
@@ -323,7 +338,7 @@ __device__ __forceinline__ void ntt_inv(double* s, Store store, const double* __
   double c[16];
   ntt_inv_regs<LOGN>(s, c, itw, m, ninv);
 #pragma unroll
-  for (int w = 0; w < 16; ++w) store((int)threadIdx.x + w * T, c[w]);
+  for (int w = 0; w < 16; ++w) store((int)opaque_tid() + w * T, c[w]);
 }
 
 
@@ -343,7 +358,7 @@ struct OrbitWalk {
   uint32_t e;  // 5^(tid + w N/16) mod 2N for the thread's current w
   template <int LOGN>
   __device__ __forceinline__ static OrbitWalk start() {  // 5^tid mod 2N, tid < N/16
-    const uint32_t mask = (2u << LOGN) - 1u, tid = threadIdx.x;
+    const uint32_t mask = (2u << LOGN) - 1u, tid = opaque_tid();
     uint32_t r = 1, b = 5;
 #pragma unroll
     for (int k = 0; k < LOGN - 4; ++k) {
@@ -400,8 +415,8 @@ __device__ __forceinline__ void ntt_fwd_regs_out(double* s, const double (&c)[Nt
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        out((int)threadIdx.x + (w + h) * T, v[2 * h]);
-        out((int)threadIdx.x + (w + h) * T + N / 2, v[2 * h + 1]);
+        out((int)opaque_tid() + (w + h) * T, v[2 * h]);
+        out((int)opaque_tid() + (w + h) * T + N / 2, v[2 * h + 1]);
       }
     }
   } else {
@@ -416,7 +431,7 @@ __device__ __forceinline__ void ntt_fwd_regs_out(double* s, const double (&c)[Nt
         x[w] = h ? U - V : U + V;
       }
       ntt_fwd_regs<14>(s, x, tw + h * H, m);
-      for (int t = h * (N / 2) + (int)threadIdx.x; t < (h + 1) * (N / 2); t += T) out(t, s[lds_pad(perm[t] - h * H)]);
+      for (int t = h * (N / 2) + (int)opaque_tid(); t < (h + 1) * (N / 2); t += T) out(t, s[lds_pad(perm[t] - h * H)]);
     }
   }
 }
@@ -428,7 +443,7 @@ __device__ __forceinline__ void ntt_fwd_out(double* s, Load load, const double* 
   constexpr int T = NttShape<LOGN>::T, PER = NttShape<LOGN>::PER;
   double c[PER];
 #pragma unroll
-  for (int w = 0; w < PER; ++w) c[w] = load((int)threadIdx.x + w * T);
+  for (int w = 0; w < PER; ++w) c[w] = load((int)opaque_tid() + w * T);
   ntt_fwd_regs_out<LOGN>(s, c, tw, perm, m, out);
 }
 
@@ -444,7 +459,7 @@ __device__ __forceinline__ void ntt_inv_in_regs(double* s, In in, const double* 
     OrbitWalk ow = OrbitWalk::start<LOGN>();
 #pragma unroll 2
     for (int w = 0; w < 8; ++w) {
-      const int t = (int)threadIdx.x + w * T, j = ow.brv_index<LOGN>();
+      const int t = (int)opaque_tid() + w * T, j = ow.brv_index<LOGN>();
       s[lds_pad(j)] = reduce(in(t), m);
       s[lds_pad(j ^ (N - 1))] = reduce(in(t + N / 2), m);
       ow.next<LOGN>();
@@ -454,11 +469,11 @@ __device__ __forceinline__ void ntt_inv_in_regs(double* s, In in, const double* 
   } else {
     constexpr int H = 1 << 14;
     double c0[16], c1[16];
-    for (int t = threadIdx.x; t < N / 2; t += T) s[lds_pad(perm[t])] = reduce(in(t), m);
+    for (int t = opaque_tid(); t < N / 2; t += T) s[lds_pad(perm[t])] = reduce(in(t), m);
     __syncthreads();
     ntt_inv_regs<14>(s, c0, itw, m, ninv);
     __syncthreads();
-    for (int t = N / 2 + (int)threadIdx.x; t < N; t += T) s[lds_pad(perm[t] - H)] = reduce(in(t), m);
+    for (int t = N / 2 + (int)opaque_tid(); t < N; t += T) s[lds_pad(perm[t] - H)] = reduce(in(t), m);
     __syncthreads();
     ntt_inv_regs<14>(s, c1, itw + H, m, ninv);
     const double iw0 = itw[0];
@@ -478,7 +493,7 @@ __device__ __forceinline__ void ntt_inv_in(double* s, In in, const double* __res
   double c[PER];
   ntt_inv_in_regs<LOGN>(s, in, itw, perm, m, ninv, c);
 #pragma unroll
-  for (int w = 0; w < PER; ++w) store((int)threadIdx.x + w * T, c[w]);
+  for (int w = 0; w < PER; ++w) store((int)opaque_tid() + w * T, c[w]);
 }
 
 }  // namespace pvfl
