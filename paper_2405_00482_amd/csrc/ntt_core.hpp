@@ -53,7 +53,6 @@ struct NttShape {
   static constexpr int T = (1 << LOGH) / 16;    // threads per workgroup
   static constexpr int PER = N / T;             // coefficients per thread: 16, or 32 at 2^15
   static constexpr int LDS = (1 << LOGH) + (1 << LOGH) / 16;  // padded LDS doubles
-  static constexpr int S0 = LOGH - 12;          // stages of the inverse's last (large-span) pass
 };
 
 __device__ __forceinline__ int lds_pad(int j) { return j + (j >> 4); }
@@ -86,34 +85,6 @@ __device__ __forceinline__ void pass_bases(int (&base)[16 >> S], int ls) {
   for (int q = 0; q < (16 >> S); ++q) {
     const unsigned c = (unsigned)(q * T) + opaque_tid();
     base[q] = (int)(((c >> ls) << (ls + S)) | (c & ((1u << ls) - 1u)));
-  }
-}
-
-// Padded addresses of a set: the passes use spans 2^ls with ls = 0 or ls >= 4.
-// For ls >= 4, u 2^ls is a multiple of 16, so lds_pad(base + u 2^ls) =
-// lds_pad(base) + u (2^ls + 2^(ls-4)); for ls = 0 the set lies inside one
-// aligned run of 16 (base is a multiple of the set size), so the padded
-// addresses are consecutive.  Either way one add per element.
-__device__ __forceinline__ int lds_set_step(int ls) { return (1 << ls) + ((1 << ls) >> 4); }
-
-template <int S>
-__device__ __forceinline__ void lds_load_sets(const double* s, double (&x)[16], const int (&base)[16 >> S], int ls) {
-  const int d = lds_set_step(ls);
-#pragma unroll
-  for (int q = 0; q < (16 >> S); ++q) {
-    const double* p = s + lds_pad(base[q]);
-#pragma unroll
-    for (int u = 0; u < (1 << S); ++u) x[q * (1 << S) + u] = p[u * d];
-  }
-}
-template <int S>
-__device__ __forceinline__ void lds_store_sets(double* s, const double (&x)[16], const int (&base)[16 >> S], int ls) {
-  const int d = lds_set_step(ls);
-#pragma unroll
-  for (int q = 0; q < (16 >> S); ++q) {
-    double* p = s + lds_pad(base[q]);
-#pragma unroll
-    for (int u = 0; u < (1 << S); ++u) p[u * d] = x[q * (1 << S) + u];
   }
 }
 
@@ -300,34 +271,52 @@ __device__ __forceinline__ void gs_pass_regs(double (&x)[16], int lg1, const int
 // barrier).  On return c[w] is coefficient tid + w*T of the natural-order
 // result times N^-1, centred.  LDS is still being read by other threads when
 // this returns: barrier before writing `s` again (ntt_fwd_regs does).
+// Schedule (the forward one mirrored): the first LOGN - 4 stages (spans 1
+// .. N/32) stay inside wave w's 1024 elements [1024 w, 1024 w + 1024) --
+// LOGN - 12 stages on sets of consecutive elements, then two radix-16
+// passes -- with wave-local LDS exchanges; after one workgroup barrier the
+// last four stages (spans N/16 .. N/2) run on the thread's own coefficients
+// {tid + u N/16}.
 template <int LOGN>
 __device__ __forceinline__ void ntt_inv_regs(double* s, double (&c)[16], const double* __restrict__ itw, ModQ m,
                                              double ninv) {
-  constexpr int S0 = NttShape<LOGN>::S0;
+  static_assert(LOGN >= 12 && LOGN <= 14, "one wave owns 1024 elements of an LDS-resident limb");
   double x[16];
-  int lg1 = LOGN - 1;
-  constexpr int NFULL = S0 > 0 ? 3 : 2;
-#pragma unroll 1
-  for (int p = 0; p < NFULL; ++p, lg1 -= 4) {
-    const int ls = LOGN - 1 - lg1;
-    int base[1];
-    pass_bases<LOGN, 4>(base, ls);
-    lds_load_sets<4>(s, x, base, ls);
-    gs_pass_regs<LOGN, 4>(x, lg1, base, itw, m);
-    lds_store_sets<4>(s, x, base, ls);
-    __syncthreads();
+  const int tid = opaque_tid();
+  if constexpr (LOGN > 12) {  // stages of span 1 .. 2^(S-1): sets of 2^S consecutive elements
+    constexpr int S = LOGN - 12, NQ = 16 >> S;
+    int base[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) base[q] = 16 * tid + (q << S);
+    lds_load_c<S, 0>(s, x, base);
+    gs_pass_regs<LOGN, S>(x, LOGN - 1, base, itw, m);
+    lds_store_c<S, 0>(s, x, base);
+    wave_lds_sync();
   }
-  {
-    constexpr int S = S0 > 0 ? S0 : 4;
-    const int ls = LOGN - 1 - lg1;
-    int base[16 >> S];
-    pass_bases<LOGN, S>(base, ls);
-    lds_load_sets<S>(s, x, base, ls);
-    gs_pass_regs<LOGN, S>(x, lg1, base, itw, m);
+  {  // four stages from span 2^(LOGN-12)
+    constexpr int LS = LOGN - 12;
+    int base[1];
+    pass_bases<LOGN, 4>(base, LS);
+    lds_load_c<4, LS>(s, x, base);
+    gs_pass_regs<LOGN, 4>(x, 11, base, itw, m);
+    lds_store_c<4, LS>(s, x, base);
+  }
+  wave_lds_sync();
+  {  // four stages from span 2^(LOGN-8)
+    constexpr int LS = LOGN - 8;
+    int base[1];
+    pass_bases<LOGN, 4>(base, LS);
+    lds_load_c<4, LS>(s, x, base);
+    gs_pass_regs<LOGN, 4>(x, 7, base, itw, m);
+    lds_store_c<4, LS>(s, x, base);
+  }
+  __syncthreads();
+  {  // spans N/16 .. N/2 on the thread's coefficients tid + u N/16
+    const int base[1] = {tid};
+    lds_load_c<4, LOGN - 4>(s, x, base);
+    gs_pass_regs<LOGN, 4>(x, 3, base, itw, m);
 #pragma unroll
-    for (int q = 0; q < (16 >> S); ++q)
-#pragma unroll
-      for (int u = 0; u < (1 << S); ++u) c[q + u * (16 >> S)] = reduce(mulmod(x[q * (1 << S) + u], ninv, m), m);
+    for (int u = 0; u < 16; ++u) c[u] = reduce(mulmod(x[u], ninv, m), m);
   }
 }
 
