@@ -30,7 +30,17 @@ __device__ __forceinline__ double round_half_away(double x) {
 // place without a barrier in between.  At stage s a butterfly pairs elements
 // half_s = M >> (s+1) apart with twiddle W_M^(j 2^s), j = index mod half_s,
 // which for element u of a set is off + (u mod 2^(S-1-st)) * stride.
-template <int LOGN, int S, int S0, int TWSH>
+// A pass is wave-local when a wave's 64 threads own one contiguous run of
+// 512 elements: one set of 8 per thread with a stride of at most 64.
+template <int LOGN, int S, int S0>
+constexpr bool fft_pass_wave_local() {
+  return S == 3 && LOGN - 1 - S0 - S <= 6;
+}
+
+// Ends with a workgroup barrier, or only a wave-level LDS fence when this
+// pass and the next one (NEXT_LOCAL) are both wave-local: the next pass then
+// reads only what the same wave wrote.
+template <int LOGN, int S, int S0, int TWSH, bool NEXT_LOCAL>
 __device__ __forceinline__ void fft_pass(double2* a, const double2* __restrict__ tw, bool conj) {
   constexpr int LOGM = LOGN - 1, M = 1 << LOGM, T = NttShape<LOGN>::T;
   constexpr int SET = 1 << S, NS = 8 >> S;
@@ -71,7 +81,10 @@ __device__ __forceinline__ void fft_pass(double2* a, const double2* __restrict__
 #pragma unroll
     for (int u = 0; u < SET; ++u) a[cpad(base[q] + (u << LS))] = x[q * SET + u];
   }
-  __syncthreads();
+  if constexpr (fft_pass_wave_local<LOGN, S, S0>() && NEXT_LOCAL)
+    wave_lds_sync();
+  else
+    __syncthreads();
 }
 
 // TWSH = 1 runs the 2^(LOGN-1)-point transform with the table of twice that
@@ -80,10 +93,12 @@ template <int LOGN, int S0, int TWSH = 0>
 __device__ __forceinline__ void fft_passes(double2* a, const double2* __restrict__ tw, bool conj) {
   constexpr int LEFT = LOGN - 1 - S0;
   if constexpr (LEFT >= 3) {
-    fft_pass<LOGN, 3, S0, TWSH>(a, tw, conj);
+    constexpr int NLEFT = LEFT - 3;  // stages after this pass
+    constexpr bool next_local = NLEFT >= 3 && fft_pass_wave_local<LOGN, 3, S0 + 3>();
+    fft_pass<LOGN, 3, S0, TWSH, next_local>(a, tw, conj);
     fft_passes<LOGN, S0 + 3, TWSH>(a, tw, conj);
   } else if constexpr (LEFT > 0) {
-    fft_pass<LOGN, LEFT, S0, TWSH>(a, tw, conj);
+    fft_pass<LOGN, LEFT, S0, TWSH, false>(a, tw, conj);
   }
 }
 
