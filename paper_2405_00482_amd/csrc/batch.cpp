@@ -52,11 +52,16 @@ struct pvfl_batch {
   const pvfl_sk* graph_sk = nullptr;
   uint64_t graph_seed = 0;
   hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
+  hipStream_t cap_stream2 = nullptr;  // second branch of the captured graph
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool has_X = false, has_v = false, has_y = false;
   ~pvfl_batch() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (cap_stream2) (void)hipStreamDestroy(cap_stream2);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
@@ -266,8 +271,8 @@ extern "C" pvfl_status pvfl_batch_encrypt(pvfl_batch* b, const pvfl_sk* sk, uint
   return PVFL_OK;
 }
 
-extern "C" pvfl_status pvfl_batch_matmul(pvfl_batch* b, void* stream) {
-  if (!b) return fail(PVFL_E_INVALID, "null argument");
+// ModUp of every input ciphertext into digits, and P c0 (no plaintexts needed)
+static pvfl_status batch_modup(pvfl_batch* b, void* stream) {
   pvfl_ctx* c = b->ctx;
   const int N = c->N, lv = b->lv, K = b->K;
   const size_t KN = (size_t)K * N, Q = (size_t)(lv + 1) * N;
@@ -280,6 +285,15 @@ extern "C" pvfl_status pvfl_batch_matmul(pvfl_batch* b, void* stream) {
     kt.stop();
   }
   HIP_TRY(launch_scale_by_p(L, nullptr, lv, N, c->pmod_dev, b->pc, b->count, b->ct_tab));
+  return PVFL_OK;
+}
+
+// fused product over the digits and plaintexts, partial sums, ModDown
+static pvfl_status batch_product(pvfl_batch* b, void* stream) {
+  pvfl_ctx* c = b->ctx;
+  const int N = c->N, lv = b->lv, K = b->K;
+  const size_t KN = (size_t)K * N, Q = (size_t)(lv + 1) * N;
+  LaunchCtx L = launch_ctx(c, stream);
   BatchDiagArgs a{};
   a.N = N;
   a.K = K;
@@ -323,6 +337,12 @@ extern "C" pvfl_status pvfl_batch_matmul(pvfl_batch* b, void* stream) {
   return PVFL_OK;
 }
 
+extern "C" pvfl_status pvfl_batch_matmul(pvfl_batch* b, void* stream) {
+  if (!b) return fail(PVFL_E_INVALID, "null argument");
+  pvfl_status st = batch_modup(b, stream);
+  return st != PVFL_OK ? st : batch_product(b, stream);
+}
+
 extern "C" pvfl_status pvfl_batch_decrypt(pvfl_batch* b, const pvfl_sk* sk, void* stream) {
   if (!b || !sk) return fail(PVFL_E_INVALID, "null argument");
   if (!b->has_y) return fail(PVFL_E_INVALID, "batch was created without result buffers");
@@ -346,6 +366,22 @@ static pvfl_status run_phases(pvfl_batch* b, const pvfl_sk* sk, uint64_t seed, v
   return pvfl_batch_decrypt(b, sk, stream);
 }
 
+// The same phases as two branches: encryption and ModUp of the inputs on s2
+// run beside the plaintext encode on s1 (they share no buffer); s1 waits for
+// both before the fused product.
+static pvfl_status run_phases_forked(pvfl_batch* b, const pvfl_sk* sk, uint64_t seed, hipStream_t s1, hipStream_t s2) {
+  pvfl_status st;
+  HIP_TRY(hipEventRecord(b->ev_fork, s1));
+  HIP_TRY(hipStreamWaitEvent(s2, b->ev_fork, 0));
+  if ((st = pvfl_batch_encrypt(b, sk, seed, s2)) != PVFL_OK) return st;
+  if ((st = batch_modup(b, s2)) != PVFL_OK) return st;
+  HIP_TRY(hipEventRecord(b->ev_join, s2));
+  if ((st = pvfl_batch_encode(b, s1)) != PVFL_OK) return st;
+  HIP_TRY(hipStreamWaitEvent(s1, b->ev_join, 0));
+  if ((st = batch_product(b, s1)) != PVFL_OK) return st;
+  return pvfl_batch_decrypt(b, sk, s1);
+}
+
 extern "C" pvfl_status pvfl_batch_run(pvfl_batch* b, const pvfl_sk* sk, uint64_t seed, int32_t use_graph,
                                       void* stream) {
   if (!b || !sk) return fail(PVFL_E_INVALID, "null argument");
@@ -361,8 +397,11 @@ extern "C" pvfl_status pvfl_batch_run(pvfl_batch* b, const pvfl_sk* sk, uint64_t
     if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     const bool timing = b->ctx->timing_on;
     b->ctx->timing_on = false;  // no event records inside the captured graph
+    if (!b->cap_stream2) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream2, hipStreamNonBlocking));
+    if (!b->ev_fork) HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    if (!b->ev_join) HIP_TRY(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
     HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    st = run_phases(b, sk, seed, b->cap_stream);
+    st = run_phases_forked(b, sk, seed, b->cap_stream, b->cap_stream2);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     b->ctx->timing_on = timing;

@@ -12,10 +12,10 @@
 //
 // Schedule.  N/16 threads each hold 16 elements in registers; up to four
 // radix-2 stages run on them between two LDS exchanges ("passes"), so a 2^14
-// transform makes four LDS round trips instead of fourteen.  In the forward
-// transform only the first exchange crosses waves; the later passes stay
-// inside one wave's 1024 elements and need no workgroup barrier (see
-// ntt_fwd_regs).  The LDS array is padded by one double every 16 (lds_pad)
+// transform makes four LDS round trips instead of fourteen.  In either
+// direction only one exchange crosses waves; the other passes stay inside
+// one wave's 1024 elements and need no workgroup barrier (see ntt_fwd_regs
+// and ntt_inv_regs).  The LDS array is padded by one double every 16 (lds_pad)
 // so that the strided set loads of every pass are close to bank-conflict
 // free.  The orbit-order permutation is computed from powers of 5 (OrbitWalk)
 // rather than read from a table, up to N = 2^14.
@@ -76,8 +76,7 @@ static __device__ __forceinline__ int opaque_tid() {
 // elements {base + u * 2^ls} (2^ls = span of the pass's last stage); thread
 // tid owns sets c = q*T + tid, q < 16 / 2^S, with base = blk * 2^(ls+S) + off,
 // blk = c >> ls, off = c mod 2^ls.  Strides are powers of two, so the index
-// arithmetic is shifts and masks.  (The pass loops stay rolled: unrolling
-// them lets the scheduler overlap passes and the register file overflows.)
+// arithmetic is shifts and masks.
 template <int LOGN, int S>
 __device__ __forceinline__ void pass_bases(int (&base)[16 >> S], int ls) {
   constexpr int T = NttShape<LOGN>::T;
