@@ -353,8 +353,12 @@ extern "C" pvfl_status pvfl_batch_decrypt(pvfl_batch* b, const pvfl_sk* sk, void
   if (st != PVFL_OK) return st;
   LaunchCtx L = launch_ctx(c, stream);
   HIP_TRY(launch_decrypt_f64(L, nullptr, b->count, sk->s, b->lv, b->res, (const double* const*)b->out_tab));
-  HIP_TRY(launch_decode(L, b->res, b->count, b->lv, crt, et, b->inv_scale, b->z));
-  HIP_TRY(launch_readout_batch(L, b->z, b->args_ct, b->prods, b->count, b->max_rows, c->N / 2));
+  if (c->logN <= 14) {  // the slots never leave LDS
+    HIP_TRY(launch_decode_readout_batch(L, b->res, b->count, b->lv, crt, et, b->inv_scale, b->args_ct, b->prods));
+  } else {
+    HIP_TRY(launch_decode(L, b->res, b->count, b->lv, crt, et, b->inv_scale, b->z));
+    HIP_TRY(launch_readout_batch(L, b->z, b->args_ct, b->prods, b->count, b->max_rows, c->N / 2));
+  }
   return PVFL_OK;
 }
 

@@ -274,6 +274,22 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_ct_batch(const Enc
 }
 
 // read-out of product p's decoded slots z[p][N/2] into its y (lazy RaS)
+// output row idx of a product from its decoded slots slot(j): the lazy
+// rotate-and-sum, added in slot order
+template <class Slot>
+__device__ __forceinline__ double readout_row(const EncodeArgs& a, int idx, Slot slot) {
+  double acc = 0.0;
+  if (a.kind == 0) {
+    const int rr = idx, g = rr / a.mprime, rho = rr % a.mprime;
+    for (int t2 = 0; t2 < a.bn / a.mprime; ++t2) acc += slot(g * a.bn + rho + t2 * a.mprime);
+  } else if (a.bm >= a.bn) {
+    acc = slot(idx);
+  } else {
+    for (int t2 = 0; t2 < a.bn / a.bm; ++t2) acc += slot(idx + t2 * a.bm);
+  }
+  return acc;
+}
+
 __global__ __launch_bounds__(256) void k_readout_batch(const double* __restrict__ z, const EncodeArgs* __restrict__ args,
                                                        const BatchProd* __restrict__ prods, int slots) {
   const int p = blockIdx.y;
@@ -281,16 +297,25 @@ __global__ __launch_bounds__(256) void k_readout_batch(const double* __restrict_
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= a.m) return;
   const double* zp = z + (size_t)p * slots;
-  double acc = 0.0;
-  if (a.kind == 0) {
-    const int rr = idx, g = rr / a.mprime, rho = rr % a.mprime;
-    for (int t2 = 0; t2 < a.bn / a.mprime; ++t2) acc += zp[g * a.bn + rho + t2 * a.mprime];
-  } else if (a.bm >= a.bn) {
-    acc = zp[idx];
-  } else {
-    for (int t2 = 0; t2 < a.bn / a.bm; ++t2) acc += zp[idx + t2 * a.bm];
-  }
-  prods[p].y[idx] = acc;
+  prods[p].y[idx] = readout_row(a, idx, [&](int j) { return zp[j]; });
+}
+
+// Decode and read-out in one workgroup per product (N <= 2^14): the slots
+// stay in LDS and each row's sum reads them there.  Same values and the same
+// order of additions as k_decode followed by k_readout_batch.
+template <int LOGN>
+__global__ __launch_bounds__(NttShape<LOGN>::T) void k_decode_readout_batch(const double* __restrict__ res, int lv,
+                                                                            CrtTabs ct, EncTabs et, double inv_scale,
+                                                                            const EncodeArgs* __restrict__ args,
+                                                                            const BatchProd* __restrict__ prods) {
+  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
+  __shared__ double2 w[NttShape<LOGN>::LDS / 2];
+  const int p = blockIdx.x;
+  decode_to_lds<LOGN>(res + (size_t)p * (lv + 1) * N, lv + 1, ct, et, w);
+  const EncodeArgs a = args[p];
+  double* y = prods[p].y;
+  for (int idx = threadIdx.x; idx < a.m; idx += T)
+    y[idx] = readout_row(a, idx, [&](int j) { return decoded_slot<LOGN>(w, et, j, inv_scale); });
 }
 
 // ---------------------------------------------------------------------------
@@ -388,6 +413,20 @@ hipError_t launch_encode_ct_batch(const LaunchCtx& L, const EncodeArgs* args, in
   return hipGetLastError();
 }
 
+template <int LOGN>
+static void decode_readout_impl(const LaunchCtx& L, const double* res, int count, int lv, const CrtTabs& ct,
+                                const EncTabs& et, double inv_scale, const EncodeArgs* args, const BatchProd* prods) {
+  if constexpr (LOGN <= 14)
+    hipLaunchKernelGGL(k_decode_readout_batch<LOGN>, dim3(count), dim3(NttShape<LOGN>::T), 0, L.stream, res, lv, ct, et,
+                       inv_scale, args, prods);
+}
+hipError_t launch_decode_readout_batch(const LaunchCtx& L, const double* res, int count, int lv, const CrtTabs& ct,
+                                       const EncTabs& et, double inv_scale, const EncodeArgs* args,
+                                       const BatchProd* prods) {
+  if (L.logN > 14) return hipErrorInvalidValue;
+  DISPATCH_LOGN(L, decode_readout_impl, L, res, count, lv, ct, et, inv_scale, args, prods);
+  return hipGetLastError();
+}
 hipError_t launch_readout_batch(const LaunchCtx& L, const double* z, const EncodeArgs* args, const BatchProd* prods,
                                 int count, int max_rows, int slots) {
   hipLaunchKernelGGL(k_readout_batch, dim3((max_rows + 255) / 256, count), dim3(256), 0, L.stream, z, args, prods, slots);

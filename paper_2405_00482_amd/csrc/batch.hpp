@@ -63,6 +63,10 @@ hipError_t launch_sum_partials_batch(const LaunchCtx& L, const double* part, con
 hipError_t launch_encode_pt_batch(const LaunchCtx& L, const EncodeArgs* args, const int2* work, int nwork,
                                   const BatchProd* prods, const EncTabs& et, LimbMap map);
 hipError_t launch_encode_ct_batch(const LaunchCtx& L, const EncodeArgs* args, int count, const EncTabs& et, int64_t* msg);
+// decode and lazy read-out of every product's decrypted residues (N <= 2^14)
+hipError_t launch_decode_readout_batch(const LaunchCtx& L, const double* res, int count, int lv, const CrtTabs& ct,
+                                       const EncTabs& et, double inv_scale, const EncodeArgs* args,
+                                       const BatchProd* prods);
 hipError_t launch_readout_batch(const LaunchCtx& L, const double* z, const EncodeArgs* args, const BatchProd* prods,
                                 int count, int max_rows, int slots);
 

@@ -7,6 +7,8 @@
 #include "encode.hpp"
 #include "ntt_core.hpp"
 
+#include <type_traits>
+
 namespace pvfl {
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -120,6 +122,70 @@ __device__ __forceinline__ void fft_dif_half15(double2* a, const double2* __rest
 }
 
 __device__ __forceinline__ int brev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
+
+// Centred CRT lift (Garner mixed radix) of coefficient kk from its residues
+// base[i N + kk], i < nl.  NL > 0 fixes the limb count at compile time, so
+// the mixed-radix digits stay in registers; NL = 0 takes nl at run time.
+template <int NL>
+__device__ __forceinline__ double crt_lift(const double* __restrict__ base, int kk, int N, const CrtTabs& ct,
+                                           int nl_rt) {
+  const int nl = NL > 0 ? NL : nl_rt;
+  double v[NL > 0 ? NL : kMaxLimbs];
+#pragma unroll
+  for (int i = 0; i < nl; ++i) {
+    const ModQ m = ct.mods[i];
+    double x = base[(size_t)i * N + kk];
+#pragma unroll
+    for (int j = 0; j < i; ++j) x = mulmod(x - v[j], ct.garner_inv[j * kMaxLimbs + i], m);
+    v[i] = canon(x, m);
+  }
+  // sign: compare with the mixed-radix digits of (Q-1)/2 from the top
+  int cmp = 0;
+#pragma unroll
+  for (int i = nl - 1; i >= 0; --i) {
+    const double h2 = 0.5 * (ct.mods[i].q - 1.0);
+    if (cmp == 0) cmp = (v[i] > h2) ? 1 : ((v[i] < h2) ? -1 : 0);
+  }
+  double acc = (cmp > 0) ? v[nl - 1] - ct.mods[nl - 1].q : v[nl - 1];
+#pragma unroll
+  for (int i = nl - 2; i >= 0; --i) acc = acc * ct.mods[i].q + v[i];
+  return acc;
+}
+
+// Decode of one ciphertext's coefficient residues base[i N + k] (i < nl,
+// canonical) up to the slot values, N <= 2^14: CRT lift, twist, DFT with sign
+// +1; the spectrum is left in LDS (w, padded, bit-reversed order) for
+// decoded_slot().  Ends with a barrier.
+template <int LOGN>
+__device__ __forceinline__ void decode_to_lds(const double* __restrict__ base, int nl, const CrtTabs& ct,
+                                              const EncTabs& et, double2* w) {
+  static_assert(LOGN <= 14, "the 2^15 ring's decode splits its FFT in halves");
+  constexpr int N = 1 << LOGN, M = N / 2, T = NttShape<LOGN>::T;
+  // twisted w_k = (m_k + i m_(k+N/2)) zeta^k
+  auto fill = [&](auto nl_c) {
+    constexpr int NL = decltype(nl_c)::value;
+    for (int k = opaque_tid(); k < M; k += T)
+      w[cpad(k)] = cmul(make_double2(crt_lift<NL>(base, k, N, ct, nl), crt_lift<NL>(base, k + M, N, ct, nl)),
+                        et.twist[k]);
+  };
+  switch (nl) {  // the usual output levels get register-resident digits
+    case 1: fill(std::integral_constant<int, 1>()); break;
+    case 2: fill(std::integral_constant<int, 2>()); break;
+    case 3: fill(std::integral_constant<int, 3>()); break;
+    case 4: fill(std::integral_constant<int, 4>()); break;
+    case 5: fill(std::integral_constant<int, 5>()); break;
+    case 6: fill(std::integral_constant<int, 6>()); break;
+    default: fill(std::integral_constant<int, 0>()); break;
+  }
+  __syncthreads();
+  fft_dif_lds<LOGN>(w, et.fft_tw, true);
+}
+
+// slot j of the spectrum decode_to_lds left in LDS, as a cleartext value
+template <int LOGN>
+__device__ __forceinline__ double decoded_slot(const double2* w, const EncTabs& et, int j, double inv_scale) {
+  return w[cpad(brev(et.slot2f[j], LOGN - 1))].x * inv_scale;
+}
 
 // Element of X that slot s of plaintext k holds (a KIND plan), or -1 where the
 // slot is zero (padding, outside the matrix).

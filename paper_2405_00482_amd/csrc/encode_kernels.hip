@@ -14,8 +14,6 @@
 
 #include "encode_dev.hpp"
 
-#include <type_traits>
-
 namespace pvfl {
 
 // One workgroup per plaintext: pack, encode, then every limb reduced and
@@ -44,35 +42,6 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode_ct_msg(EncodeArgs 
   }
 }
 
-// Centred CRT lift (Garner mixed radix) of coefficient kk from its residues
-// base[i N + kk], i < nl.  NL > 0 fixes the limb count at compile time, so
-// the mixed-radix digits stay in registers; NL = 0 takes nl at run time.
-template <int NL>
-__device__ __forceinline__ double crt_lift(const double* __restrict__ base, int kk, int N, const CrtTabs& ct,
-                                           int nl_rt) {
-  const int nl = NL > 0 ? NL : nl_rt;
-  double v[NL > 0 ? NL : kMaxLimbs];
-#pragma unroll
-  for (int i = 0; i < nl; ++i) {
-    const ModQ m = ct.mods[i];
-    double x = base[(size_t)i * N + kk];
-#pragma unroll
-    for (int j = 0; j < i; ++j) x = mulmod(x - v[j], ct.garner_inv[j * kMaxLimbs + i], m);
-    v[i] = canon(x, m);
-  }
-  // sign: compare with the mixed-radix digits of (Q-1)/2 from the top
-  int cmp = 0;
-#pragma unroll
-  for (int i = nl - 1; i >= 0; --i) {
-    const double h2 = 0.5 * (ct.mods[i].q - 1.0);
-    if (cmp == 0) cmp = (v[i] > h2) ? 1 : ((v[i] < h2) ? -1 : 0);
-  }
-  double acc = (cmp > 0) ? v[nl - 1] - ct.mods[nl - 1].q : v[nl - 1];
-#pragma unroll
-  for (int i = nl - 2; i >= 0; --i) acc = acc * ct.mods[i].q + v[i];
-  return acc;
-}
-
 // Decode: centred CRT lift of decrypted coefficient residues [nct][l+1][N]
 // (canonical, binary64), twist, DFT with sign +1, slots z[c][j] =
 // Re(.)/scale.
@@ -89,24 +58,8 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_decode(const double* __re
   auto twisted = [&](int k) { return cmul(make_double2(lift(k), lift(k + M)), et.twist[k]); };
   double* zc = z + (size_t)c * M;
   if constexpr (LOGN <= 14) {
-    auto fill = [&](auto nl_c) {
-      constexpr int NL = decltype(nl_c)::value;
-      for (int k = threadIdx.x; k < M; k += T)
-        w[cpad(k)] = cmul(make_double2(crt_lift<NL>(base, k, N, ct, nl), crt_lift<NL>(base, k + M, N, ct, nl)),
-                          et.twist[k]);
-    };
-    switch (nl) {  // the usual output levels get register-resident digits
-      case 1: fill(std::integral_constant<int, 1>()); break;
-      case 2: fill(std::integral_constant<int, 2>()); break;
-      case 3: fill(std::integral_constant<int, 3>()); break;
-      case 4: fill(std::integral_constant<int, 4>()); break;
-      case 5: fill(std::integral_constant<int, 5>()); break;
-      case 6: fill(std::integral_constant<int, 6>()); break;
-      default: fill(std::integral_constant<int, 0>()); break;
-    }
-    __syncthreads();
-    fft_dif_lds<LOGN>(w, et.fft_tw, true);
-    for (int j = threadIdx.x; j < M; j += T) zc[j] = w[cpad(brev(et.slot2f[j], LOGN - 1))].x * inv_scale;
+    decode_to_lds<LOGN>(base, nl, ct, et, w);
+    for (int j = threadIdx.x; j < M; j += T) zc[j] = decoded_slot<LOGN>(w, et, j, inv_scale);
   } else {
     // first DIF stage (pairs k, k + M/2) in registers, then the two halves in LDS
     constexpr int HM = M / 2;
