@@ -229,11 +229,20 @@ __global__ __launch_bounds__(256) void k_sum_partials_batch(const double* __rest
   const int nch = (B.mprime + CH - 1) / CH;
   const int r = (int)((idx / N) % K);
   const ModQ m = mods[limb_prime.idx[r]];
+  // eight partials' loads in flight at a time, added in chunk order with a
+  // re-centring after every eighth (|v| < 8.5 q): the per-call form's sum
+  const double* src = part + (size_t)B.part0 * tot + idx;
   double v = 0.0;
-  for (int c = 0; c < nch; ++c) {
-    v += part[(size_t)(B.part0 + c) * tot + idx];
-    if ((c & 7) == 7) v = reduce(v, m);
+  int c = 0;
+  for (; c + 8 <= nch; c += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = __builtin_nontemporal_load(src + (size_t)(c + u) * tot);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+    v = reduce(v, m);
   }
+  for (; c < nch; ++c) v += __builtin_nontemporal_load(src + (size_t)c * tot);
   acc[(size_t)p * tot + idx] = reduce(v, m);
 }
 
