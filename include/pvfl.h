@@ -7,7 +7,7 @@
  * result goes back to the key owner, who only decrypts it (characteristic C3,
  * Sec. 4).  The matrix form [[A]] W of Alg. 3 (Sec. 5.3) is also supported.
  * The encryption is RNS-CKKS (the paper's implementation uses Lattigo CKKS,
- * Sec. 6) with hybrid key switching.
+ * Sec. 7) with hybrid key switching.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -64,7 +64,7 @@ typedef struct pvfl_plan pvfl_plan;
  * p: n_p special primes of the key-switching modulus P (alpha = n_p, so the
  * digit count at level l is ceil((l+1)/alpha)).  Copied by the library. */
 typedef struct {
-  uint32_t log_n;      /* ring degree N = 2^log_n, 12..14 */
+  uint32_t log_n;      /* ring degree N = 2^log_n, 12..15 */
   uint32_t n_q;
   uint32_t n_p;
   const uint64_t* q;

@@ -10,7 +10,7 @@
  * of computing a negacyclic product, never as a storage format, so its choice
  * of root and ordering is invisible to callers.
  *
- * Sources of the mathematics (the paper only names "Lattigo CKKS", Sec. 6):
+ * Sources of the mathematics (the paper only names "Lattigo CKKS", Sec. 7):
  *   - RLWE encryption/decryption: Sec. 2.2 (Packed Homomorphic Encryption).
  *   - full-RNS CKKS base conversion: Cheon-Han-Kim-Kim-Song, SAC 2018, and
  *     Bajard-Eynard-Hasan-Zucca, SAC 2016 (fast base extension, no overflow

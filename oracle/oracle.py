@@ -6,7 +6,7 @@ library: the scalar arithmetic lives in ``ckks_oracle.c`` (``__int128`` and
 ``%``), the orchestration below follows the paper's steps in its notation.
 
 Conventions (every one of them is part of the contract the GPU path must
-meet bit for bit; the paper itself only says "Lattigo CKKS", Sec. 6):
+meet bit for bit; the paper itself only says "Lattigo CKKS", Sec. 7):
 
 * Ring Z_Q[X]/(X^N+1), N' = N/2 slots (Sec. 2.2).  RNS primes q_0..q_L for the
   ciphertext modulus and p_0..p_{alpha-1} for the key-switching modulus P.

@@ -405,7 +405,8 @@ def encode_residues(params: O.Params, slots_vec, scale: float, primes) -> np.nda
     return O.reduce_signed(m, primes)
 
 
-def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool, hoisted: bool = True) -> list:
+def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool, hoisted: bool = True,
+                  workers: int = 1) -> list:
     """Evaluate the hybrid plan (or any plan given as `terms()`).
 
     cts: input ciphertexts (coefficient domain); pt_ints: integer coefficient
@@ -419,6 +420,10 @@ def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool, 
     hoisted = False (eager only): every rotation a complete O3 rotation
       (automorphism, then its own ModUp; Sec. 2), once per term -- the cost
       profile of GALA's method (Table 2).
+    workers > 1 (lazy only): the independent rotated terms, and the
+      accumulation of each (output, limb) pair, run on that many threads (the
+      C core releases the interpreter lock); every sum still takes the terms
+      in terms() order, so the residues are the same as with one worker.
     """
     assert hoisted or not lazy, "unhoisted rotations are evaluated with per-rotation ModDown"
     N = params.N
@@ -449,17 +454,33 @@ def hybrid_matmul(params: O.Params, plan, cts, pt_ints, keys: dict, lazy: bool, 
         return outs
     acc0 = [np.zeros((len(QPp), N), dtype=np.uint64) for _ in range(n_out)]
     acc1 = [np.zeros((len(QPp), N), dtype=np.uint64) for _ in range(n_out)]
-    term_cache = {}
-    for (c, i, k, b) in terms:
-        if (c, i) not in term_cache:
-            term_cache[(c, i)] = lazy_term(params, cts[c], digits[c], keys, i)
-        t0, t1 = term_cache[(c, i)]
-        pt = O.reduce_signed(pt_ints[k], QPp)
-        for r, mod in enumerate(QPp):
-            acc0[b][r] = O.poly_add(acc0[b][r], O.poly_mul(pt[r], t0[r], mod), mod)
-            acc1[b][r] = O.poly_add(acc1[b][r], O.poly_mul(pt[r], t1[r], mod), mod)
+    pairs = list(dict.fromkeys((c, i) for (c, i, k, b) in terms))
+    term_cache = dict(zip(pairs, _pmap(lambda ci: lazy_term(params, cts[ci[0]], digits[ci[0]], keys, ci[1]),
+                                       pairs, workers)))
+
+    def accumulate(br):
+        b, r = br
+        mod = QPp[r]
+        for (c, i, k, bb) in terms:
+            if bb != b:
+                continue
+            t0, t1 = term_cache[(c, i)]
+            pt = O.reduce_signed(pt_ints[k], [mod])[0]
+            acc0[b][r] = O.poly_add(acc0[b][r], O.poly_mul(pt, t0[r], mod), mod)
+            acc1[b][r] = O.poly_add(acc1[b][r], O.poly_mul(pt, t1[r], mod), mod)
+
+    _pmap(accumulate, [(b, r) for b in range(n_out) for r in range(len(QPp))], workers)
     return [O.Ciphertext(O.moddown(params, lv, acc0[b]), O.moddown(params, lv, acc1[b]), lv)
             for b in range(n_out)]
+
+
+def _pmap(fn, items, workers: int) -> list:
+    """[fn(x) for x in items], on `workers` threads when workers > 1"""
+    if workers <= 1:
+        return [fn(x) for x in items]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(fn, items))
 
 
 def lazy_term(params: O.Params, ct, digits, keys: dict, i: int):

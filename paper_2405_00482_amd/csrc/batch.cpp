@@ -130,6 +130,8 @@ extern "C" pvfl_status pvfl_batch_create(pvfl_ctx* c, int32_t count, const pvfl_
       for (uint32_t g : p->galois)
         if (keys->slot_of_rot[c->log5[g]] < 0) return fail(PVFL_E_NOKEY, "missing rotation key");
     }
+    if (X_dev && ldx && ldx[k] < p->info.n)
+      return fail(PVFL_E_SHAPE, "product " + std::to_string(k) + ": leading dimension smaller than the row length");
     BatchProd& B = prods[k];
     B.ct = (const double*)ct_dev[k];
     B.ct_out = (double*)ct_dev[k];

@@ -9,9 +9,6 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
-
-import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpvfl.so")
@@ -184,6 +181,39 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+E_INVALID, E_SHAPE = -1, -2
+
+
+def _dev(t, what: str, nbytes: int = 0, dtype: str = "float64") -> ctypes.c_void_p:
+    """the device pointer of t after checking that it is a contiguous device
+    tensor of the given dtype holding at least nbytes; the library reads and
+    writes raw device memory, so a wrong tensor is refused here instead"""
+    if t is None:
+        raise PvflError(E_INVALID, f"{what}: a device tensor is required")
+    if str(t.dtype) != "torch." + dtype or not t.is_cuda or not t.is_contiguous():
+        raise PvflError(E_INVALID, f"{what}: expected a contiguous {dtype} device tensor, got {t.dtype} "
+                                   f"on {t.device}{'' if t.is_contiguous() else ', not contiguous'}")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise PvflError(E_SHAPE, f"{what}: {have} bytes, the call needs {nbytes}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_rows(t, what: str, rows: int, cols: int):
+    """a float64 device matrix of at least rows x cols with unit column stride
+    (a vector counts as one row); returns (pointer, row stride)"""
+    if t is None or str(t.dtype) != "torch.float64" or not t.is_cuda:
+        raise PvflError(E_INVALID, f"{what}: expected a float64 device tensor")
+    if t.dim() == 1:
+        if rows > 1 or t.numel() < cols or t.stride(0) != 1:
+            raise PvflError(E_SHAPE, f"{what}: a vector of {t.numel()} cannot hold {rows} x {cols}")
+        return ctypes.c_void_p(t.data_ptr()), t.numel()
+    if t.dim() != 2 or t.stride(1) != 1 or t.shape[0] < rows or t.shape[1] < cols or t.stride(0) < t.shape[1]:
+        raise PvflError(E_SHAPE, f"{what}: need a row-major {rows} x {cols} matrix with unit column stride, "
+                                 f"got shape {tuple(t.shape)} strides {tuple(t.stride())}")
+    return ctypes.c_void_p(t.data_ptr()), t.stride(0)
+
+
 class _Handle:
     _destroy = ""
 
@@ -277,48 +307,79 @@ class Context(_Handle):
         _check(lib().pvfl_timing_read(self.h, cls, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
         return ms.value, n.value, by.value
 
+    # byte sizes of residue arrays at a level
+    def _limbs(self, level: int, with_p: bool = False) -> int:
+        lv = self.L if level < 0 else level
+        return lv + 1 + (self.alpha if with_p else 0)
+
+    def _ct_bytes(self, level: int) -> int:
+        return 16 * self._limbs(level) * self.N
+
     # integer-level entries
     def pt_import(self, level: int, with_p: bool, m_i64, out):
         count = m_i64.shape[0]
-        _check(lib().pvfl_pt_import(self.h, level, int(with_p), _ptr(m_i64), count, _ptr(out), _stream()))
+        m = _dev(m_i64, "coefficients", 8 * count * self.N, "int64")
+        o = _dev(out, "plaintexts", 8 * count * self._limbs(level, with_p) * self.N)
+        _check(lib().pvfl_pt_import(self.h, level, int(with_p), m, count, o, _stream()))
 
     def encrypt_coeffs(self, sk, level: int, m_i64, seed: int, out):
-        _check(lib().pvfl_encrypt_coeffs(self.h, sk.h, level, _ptr(m_i64), seed, _ptr(out), _stream()))
+        m = _dev(m_i64, "coefficients", 8 * self.N, "int64")
+        o = _dev(out, "ciphertext", self._ct_bytes(level))
+        _check(lib().pvfl_encrypt_coeffs(self.h, sk.h, level, m, seed, o, _stream()))
 
     def encrypt_coeffs_pk(self, pk, level: int, m_i64, seed: int, out):
-        _check(lib().pvfl_encrypt_coeffs_pk(self.h, pk.h, level, _ptr(m_i64), seed, _ptr(out), _stream()))
+        m = _dev(m_i64, "coefficients", 8 * self.N, "int64")
+        o = _dev(out, "ciphertext", self._ct_bytes(level))
+        _check(lib().pvfl_encrypt_coeffs_pk(self.h, pk.h, level, m, seed, o, _stream()))
 
     def export_coeffs(self, level: int, with_p: bool, poly, count: int, out):
-        _check(lib().pvfl_export_coeffs(self.h, level, int(with_p), _ptr(poly), count, _ptr(out), _stream()))
+        nb = 8 * count * self._limbs(level, with_p) * self.N
+        src = _dev(poly, "polynomials", nb)
+        o = _dev(out, "residues", nb, "int64")
+        _check(lib().pvfl_export_coeffs(self.h, level, int(with_p), src, count, o, _stream()))
 
     def decrypt_coeffs(self, sk, level: int, ct, out):
-        _check(lib().pvfl_decrypt_coeffs(self.h, sk.h, level, _ptr(ct), _ptr(out), _stream()))
+        c = _dev(ct, "ciphertext", self._ct_bytes(level))
+        o = _dev(out, "residues", 8 * self._limbs(level) * self.N, "int64")
+        _check(lib().pvfl_decrypt_coeffs(self.h, sk.h, level, c, o, _stream()))
 
     def rotate(self, keys, level: int, ct, galois: int, hoisted: bool, out):
-        _check(lib().pvfl_rotate(self.h, keys.h, level, _ptr(ct), galois, int(hoisted), _ptr(out), _stream()))
+        nb = self._ct_bytes(level)
+        c, o = _dev(ct, "ciphertext", nb), _dev(out, "output", nb)
+        _check(lib().pvfl_rotate(self.h, keys.h, level, c, galois, int(hoisted), o, _stream()))
 
     def rescale(self, level: int, ct, out):
-        _check(lib().pvfl_rescale(self.h, level, _ptr(ct), _ptr(out), _stream()))
+        c = _dev(ct, "ciphertext", self._ct_bytes(level))
+        o = _dev(out, "output", self._ct_bytes(level - 1) if level >= 1 else 0)
+        _check(lib().pvfl_rescale(self.h, level, c, o, _stream()))
 
     def ct_mul_pt(self, level: int, ct, pt, out):
-        _check(lib().pvfl_ct_mul_pt(self.h, level, _ptr(ct), _ptr(pt), _ptr(out), _stream()))
+        nb = self._ct_bytes(level)
+        c, o = _dev(ct, "ciphertext", nb), _dev(out, "output", nb)
+        q = _dev(pt, "plaintext", nb // 2)
+        _check(lib().pvfl_ct_mul_pt(self.h, level, c, q, o, _stream()))
 
     def ct_add(self, level: int, a, b, out):
-        _check(lib().pvfl_ct_add(self.h, level, _ptr(a), _ptr(b), _ptr(out), _stream()))
+        nb = self._ct_bytes(level)
+        _check(lib().pvfl_ct_add(self.h, level, _dev(a, "a", nb), _dev(b, "b", nb), _dev(out, "output", nb),
+                                 _stream()))
 
 
 class SecretKey(_Handle):
     _destroy = "pvfl_sk_destroy"
 
     def export(self, out):
-        _check(lib().pvfl_sk_export(self.h, _ptr(out), _stream()))
+        ctx = self._keep[0]
+        _check(lib().pvfl_sk_export(self.h, _dev(out, "residues", 8 * ctx._limbs(-1, True) * ctx.N, "int64"),
+                                    _stream()))
 
 
 class PublicKey(_Handle):
     _destroy = "pvfl_pk_destroy"
 
     def export(self, out):
-        _check(lib().pvfl_pk_export(self.h, _ptr(out), _stream()))
+        ctx = self._keep[0]
+        _check(lib().pvfl_pk_export(self.h, _dev(out, "residues", ctx._ct_bytes(-1), "int64"), _stream()))
 
 
 class RotKeys(_Handle):
@@ -329,7 +390,10 @@ class RotKeys(_Handle):
         self.galois = galois
 
     def export(self, index: int, out):
-        _check(lib().pvfl_rotkeys_export(self.h, index, _ptr(out), _stream()))
+        ctx = self._keep[0]
+        beta = -(-(ctx.L + 1) // ctx.alpha)
+        nb = 8 * beta * 2 * ctx._limbs(-1, True) * ctx.N
+        _check(lib().pvfl_rotkeys_export(self.h, index, _dev(out, "residues", nb, "int64"), _stream()))
 
 
 class Plan(_Handle):
@@ -351,47 +415,79 @@ class Plan(_Handle):
     def bytes(self, what: str) -> int:
         return int(getattr(lib(), "pvfl_bytes_" + what)(self.h))
 
+    def _n_results(self) -> int:
+        i = self.info
+        return i["m"] * i["n_out"] if i["kind"] == PLAN_CTMAT else i["m"]
+
+    def _matrix(self, X, what: str):
+        """the plaintext matrix (W, n x n_out, for CTMAT): pointer and row stride"""
+        i = self.info
+        rows, cols = (i["n"], i["n_out"]) if i["kind"] == PLAN_CTMAT else (i["m"], i["n"])
+        return _dev_rows(X, what, rows, cols)
+
+    def _vector(self, v, what: str):
+        """the encrypted operand (A, m x n, for CTMAT; else y of length n): pointer and row stride"""
+        i = self.info
+        if i["kind"] == PLAN_CTMAT:
+            return _dev_rows(v, what, i["m"], i["n"])
+        return _dev_rows(v.reshape(-1) if v is not None and v.dim() == 1 else v, what, 1, i["n"])
+
     def encode_pt(self, X, out, coef: float = 1.0):
-        """X: device float64 matrix (row-major, contiguous rows); coef scales it (Eq. 4's q_1 X)."""
-        ld = X.stride(0) if X.dim() == 2 else X.numel()
+        """X: device float64 matrix (row-major, unit column stride); coef scales it (Eq. 4's q_1 X)."""
+        x, ld = self._matrix(X, "plaintext matrix")
+        o = _dev(out, "plaintexts", self.bytes("pt"))
         if coef == 1.0:
-            _check(lib().pvfl_encode_pt(self.h, _ptr(X), ld, _ptr(out), _stream()))
+            _check(lib().pvfl_encode_pt(self.h, x, ld, o, _stream()))
         else:
-            _check(lib().pvfl_encode_pt_scaled(self.h, _ptr(X), ld, float(coef), _ptr(out), _stream()))
+            _check(lib().pvfl_encode_pt_scaled(self.h, x, ld, float(coef), o, _stream()))
 
     def matmul_sum(self, cts, pts, keys, out, ws=None):
         """Eq. 4: out = sum_k product(cts[k], pts[k]) with one ModDown per output"""
         n = len(cts)
-        ca = (_VP * n)(*[t.data_ptr() for t in cts])
-        pa = (_VP * n)(*[t.data_ptr() for t in pts])
+        if len(pts) != n:
+            raise PvflError(E_INVALID, "one plaintext set per ciphertext set")
+        ca = (_VP * n)(*[_dev(t, f"ciphertexts {k}", self.bytes("ct_in")).value for k, t in enumerate(cts)])
+        pa = (_VP * n)(*[_dev(t, f"plaintexts {k}", self.bytes("pt")).value for k, t in enumerate(pts)])
+        o = _dev(out, "output", self.bytes("ct_out"))
+        w = _dev(ws, "workspace", self.workspace_sum_bytes(n)) if ws is not None else _ptr(None)
         ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
-        _check(lib().pvfl_matmul_ct_pt_sum(self.h, n, ca, pa, keys.h if keys is not None else None, _ptr(out),
-                                           _ptr(ws), ws_bytes, _stream()))
+        _check(lib().pvfl_matmul_ct_pt_sum(self.h, n, ca, pa, keys.h if keys is not None else None, o, w, ws_bytes,
+                                           _stream()))
 
     def workspace_sum_bytes(self, count: int) -> int:
         return int(lib().pvfl_bytes_workspace_sum(self.h, count))
 
+    def _slots_bytes(self) -> int:
+        return 8 * self.info["ct_out"] * (self.ctx.N // 2)
+
     def encode_out(self, v, mode: int, out):
         """cleartext at the output scale: mode OUT_ROWS (m values, inverse RaS) or OUT_SLOTS ([ct_out][N/2])"""
-        _check(lib().pvfl_encode_out(self.h, _ptr(v), mode, _ptr(out), _stream()))
+        nb = self._slots_bytes() if mode == OUT_SLOTS else 8 * self._n_results()
+        _check(lib().pvfl_encode_out(self.h, _dev(v, "values", nb), mode, _dev(out, "plaintext", self.bytes("pt_out")),
+                                     _stream()))
 
     def out_add_pt(self, ct, pt, sign: int, out):
-        _check(lib().pvfl_out_add_pt(self.h, _ptr(ct), _ptr(pt), sign, _ptr(out), _stream()))
+        nb = self.bytes("ct_out")
+        _check(lib().pvfl_out_add_pt(self.h, _dev(ct, "ciphertexts", nb), _dev(pt, "plaintext", self.bytes("pt_out")),
+                                     sign, _dev(out, "output", nb), _stream()))
 
     def lazy_ras(self, slots, out):
         """the masking party's share: lazy rotate-and-sum of cleartext slots [ct_out][N/2]"""
-        _check(lib().pvfl_lazy_ras(self.h, _ptr(slots), _ptr(out), _stream()))
+        _check(lib().pvfl_lazy_ras(self.h, _dev(slots, "slots", self._slots_bytes()),
+                                   _dev(out, "results", 8 * self._n_results()), _stream()))
 
     def encrypt(self, sk, v, seed: int, out):
-        ld = v.stride(0) if v.dim() == 2 else v.numel()
-        _check(lib().pvfl_encrypt(self.h, sk.h, _ptr(v), ld, seed, _ptr(out), _stream()))
+        x, ld = self._vector(v, "encrypted operand")
+        _check(lib().pvfl_encrypt(self.h, sk.h, x, ld, seed, _dev(out, "ciphertexts", self.bytes("ct_in")), _stream()))
 
     def encrypt_pk(self, pk, v, seed: int, out):
-        ld = v.stride(0) if v.dim() == 2 else v.numel()
-        _check(lib().pvfl_encrypt_pk(self.h, pk.h, _ptr(v), ld, seed, _ptr(out), _stream()))
+        x, ld = self._vector(v, "encrypted operand")
+        _check(lib().pvfl_encrypt_pk(self.h, pk.h, x, ld, seed, _dev(out, "ciphertexts", self.bytes("ct_in")),
+                                     _stream()))
 
     def decrypt_decode(self, sk, ct, out):
-        _check(lib().pvfl_decrypt_decode(self.h, sk.h, _ptr(ct), _ptr(out), _stream()))
+        _check(lib().pvfl_decrypt_decode(self.h, sk.h, _dev(ct, "ciphertexts", self.bytes("ct_out")),
+                                         _dev(out, "results", 8 * self._n_results()), _stream()))
 
     def transpose_galois(self) -> list:
         """Galois elements the transposed diagonal conversion (Eq. 7) needs"""
@@ -403,8 +499,9 @@ class Plan(_Handle):
 
     def transpose(self, ct_in, keys, ct_out):
         """[[A]] diagonals -> [[A^T]] diagonals (Eq. 7)"""
-        _check(lib().pvfl_ctmat_transpose(self.h, _ptr(ct_in), keys.h if keys is not None else None, _ptr(ct_out),
-                                          _stream()))
+        nb = self.bytes("ct_in")
+        _check(lib().pvfl_ctmat_transpose(self.h, _dev(ct_in, "ciphertexts", nb), keys.h if keys is not None else None,
+                                          _dev(ct_out, "output", nb), _stream()))
 
     def features(self, batch: int = 1) -> list:
         arr = (ctypes.c_float * PLAN_FEATURES)()
@@ -418,9 +515,12 @@ class Plan(_Handle):
         return out.value
 
     def matmul(self, ct, pt, keys, out, ws=None):
+        c = _dev(ct, "ciphertexts", self.bytes("ct_in"))
+        p = _dev(pt, "plaintexts", self.bytes("pt"))
+        o = _dev(out, "output", self.bytes("ct_out"))
+        w = _dev(ws, "workspace", self.bytes("workspace")) if ws is not None else _ptr(None)
         ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
-        _check(lib().pvfl_matmul_ct_pt(self.h, _ptr(ct), _ptr(pt), keys.h if keys is not None else None, _ptr(out),
-                                       _ptr(ws), ws_bytes, _stream()))
+        _check(lib().pvfl_matmul_ct_pt(self.h, c, p, keys.h if keys is not None else None, o, w, ws_bytes, _stream()))
 
 
 def choose_analytic(ctx: Context, m: int, n: int, costs, level: int = -1, operand: int = 0, n_out: int = 0):
@@ -479,8 +579,20 @@ class Batch(_Handle):
                  group: int = 2, chunk: int = 32, vec: int = 1, chunk_major: bool = True):
         n = len(plans)
         plan_arr = (_VP * n)(*[p.h.value for p in plans])
-        ld = (ctypes.c_int64 * n)(*[(x.stride(0) if x is not None and x.dim() == 2 else p.info["n"])
-                                    for x, p in zip(X if X is not None else [None] * n, plans)])
+        for name, lst in (("pt", pt), ("ct", ct), ("out", out), ("X", X), ("v", v), ("y", y)):
+            if lst is not None and len(lst) != n:
+                raise PvflError(E_INVALID, f"{name}: one entry per product")
+        ld = (ctypes.c_int64 * n)()
+        for k, p in enumerate(plans):
+            _dev(pt[k], f"plaintexts {k}", p.bytes("pt"))
+            _dev(ct[k], f"ciphertext {k}", p.bytes("ct_in"))
+            _dev(out[k], f"output {k}", p.bytes("ct_out"))
+            if X is not None:
+                ld[k] = p._matrix(X[k], f"plaintext matrix {k}")[1]
+            if v is not None:
+                p._vector(v[k], f"encrypted vector {k}")
+            if y is not None:
+                _dev(y[k], f"results {k}", 8 * p._n_results())
         h = _VP()
         _check(lib().pvfl_batch_create(ctx.h, n, plan_arr,
                                        _ptr_array(X) if X is not None else None, ld,
@@ -530,7 +642,7 @@ class Mlp(_Handle):
         return out
 
     def set_params(self, p):
-        _check(lib().pvfl_mlp_set_params(self.h, _ptr(p), _stream()))
+        _check(lib().pvfl_mlp_set_params(self.h, _dev(p, "parameters", 4 * self.n_params, "float32"), _stream()))
 
     def _check_x(self, x, t=None):
         import torch

@@ -1,7 +1,7 @@
 """Seeded synthetic inputs for the five workloads (no HE arithmetic here).
 
 The paper measures on SUSY (efficiency) and NUS-WIDE (accuracy), resampled in
-size (Sec. 6, Dataset); neither is available here, so seeded synthetic data of
+size (Sec. 7, Dataset); neither is available here, so seeded synthetic data of
 the workloads' shapes and value distributions stand in for them.  Both the
 HIP path and the CPU oracle are fed from these generators.
 

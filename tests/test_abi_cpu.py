@@ -38,3 +38,19 @@ def test_library_exports_every_declared_symbol():
 def test_binding_imports_without_gpu():
     from paper_2405_00482_amd import pvfl
     assert pvfl.PLAN_HYBRID == 0
+
+
+def test_binding_refuses_wrong_tensors_before_the_library():
+    """the binding checks dtype, device, contiguity and size of every buffer
+    it hands to the library (a wrong tensor would otherwise become an
+    out-of-bounds device access); a CPU tensor is refused without a GPU"""
+    import torch
+    from paper_2405_00482_amd import pvfl
+    for t, dtype, nbytes, status in ((torch.zeros(4, dtype=torch.float64), "float64", 0, pvfl.E_INVALID),
+                                     (None, "float64", 0, pvfl.E_INVALID)):
+        with pytest.raises(pvfl.PvflError) as e:
+            pvfl._dev(t, "buffer", nbytes, dtype)
+        assert e.value.status == status
+    with pytest.raises(pvfl.PvflError) as e:
+        pvfl._dev_rows(torch.zeros(3, 4, dtype=torch.float32), "matrix", 3, 4)
+    assert e.value.status == pvfl.E_INVALID

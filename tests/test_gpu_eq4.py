@@ -132,31 +132,35 @@ def test_encode_out_matches_oracle(kind, m, n, mode):
 
 
 def test_out_add_pt_and_lazy_ras():
-    """ct +- pt is exact residue arithmetic on c0 (c1 unchanged); the masking
-    party's RaS equals the oracle's"""
+    """ct +- pt is exact residue arithmetic on c0 (c1 unchanged): residues
+    equal the oracle's ct_add_plain on the oracle's ciphertext and the same
+    integer plaintext; the masking party's RaS equals the oracle's"""
     prm = O.Params.from_dict(W.params_dict("C1"))
     ctx = context("C1")
     N, lv = prm.N, prm.L
     plan = ctx.plan(0, 16, 256, lazy=True)
     oplan = PL.HybridPlan(16, 256, prm.slots)
     sk = ctx.keygen(SEED_SK)
+    s = O.keygen(prm, SEED_SK)
     rng = np.random.default_rng(5)
+    m_ints = rng.integers(-2 ** 40, 2 ** 40, N)
     ct = dev_f64(plan.bytes("ct_out") // 8)
-    ctx.encrypt_coeffs(sk, lv, dev_i64(rng.integers(-2 ** 40, 2 ** 40, N)), 7, ct)
-    mask = rng.uniform(-8, 8, prm.slots)
+    ctx.encrypt_coeffs(sk, lv, dev_i64(m_ints), 7, ct)
+    oct_ = O.encrypt(prm, s, m_ints, lv, 7)
+    p_ints = rng.integers(-2 ** 45, 2 ** 45, N)
     pt = dev_f64(plan.bytes("pt_out") // 8)
-    mask_dev = dev_f64(prm.slots)
-    mask_dev.copy_(mask_dev.new_tensor(mask))
-    plan.encode_out(mask_dev, pvfl.OUT_SLOTS, pt)
+    ctx.pt_import(lv, False, dev_i64(p_ints[None, :]), pt)
+    p_res = O.reduce_signed(p_ints, prm.q[: lv + 1])
     for sign in (1, -1):
         out = dev_f64(plan.bytes("ct_out") // 8)
         plan.out_add_pt(ct, pt, sign, out)
-        a, o = export_ct(ctx, lv, ct)[0], export_ct(ctx, lv, out)[0]
-        p = export(ctx, lv, False, pt, 1)[0]
-        for i, q in enumerate(prm.q[: lv + 1]):
-            want = (a[0, i].astype(object) + sign * p[i].astype(object)) % q
-            assert_same(o[0, i], want.astype(np.uint64), f"c0 limb {i} sign {sign}")
-        assert_same(o[1], a[1], "c1")
+        o = export_ct(ctx, lv, out)[0]
+        want = PL.ct_add_plain(prm, oct_, p_res, sign)
+        assert_same(o[0], want.c0, f"c0 sign {sign}")
+        assert_same(o[1], want.c1, f"c1 sign {sign}")
+    mask = rng.uniform(-8, 8, prm.slots)
+    mask_dev = dev_f64(prm.slots)
+    mask_dev.copy_(mask_dev.new_tensor(mask))
     y = dev_f64(16)
     plan.lazy_ras(mask_dev, y)
     np.testing.assert_allclose(y.cpu().numpy(), PL.hybrid_lazy_ras(oplan, [mask]), rtol=0, atol=1e-12)

@@ -86,3 +86,27 @@ def test_unit_shape_runs():
     p.matmul(ct, pt, None, out)
     p.decrypt_decode(sk, out, y)
     assert abs(float(y.item()) + 0.375) < 1e-6
+
+
+def test_binding_checks_tensors():
+    """dtype, device, contiguity and size of every buffer are checked before
+    the call reaches the library"""
+    t = torch()
+    ctx = context("C1")
+    sk = ctx.keygen(1)
+    p = ctx.plan(pvfl.PLAN_HYBRID, 64, 256, lazy=True)
+    keys = ctx.rotkeys(sk, p.galois(), 2)
+    ct, pt, out = (dev_f64(p.bytes(w) // 8) for w in ("ct_in", "pt", "ct_out"))
+    assert status_of(lambda: p.matmul(ct.float(), pt, keys, out)) == E_INVALID        # float32
+    assert status_of(lambda: p.matmul(ct.cpu(), pt, keys, out)) == E_INVALID          # host memory
+    assert status_of(lambda: p.matmul(ct, pt[: pt.numel() // 2], keys, out)) == E_SHAPE
+    assert status_of(lambda: p.matmul(ct, pt, keys, out[::2])) == E_INVALID          # not contiguous
+    X = t.zeros(64, 256, dtype=t.float64, device="cuda")
+    assert status_of(lambda: p.encode_pt(X[:, :100], pt)) == E_SHAPE                  # rows too short
+    assert status_of(lambda: p.encode_pt(X[:32], pt)) == E_SHAPE                      # too few rows
+    assert status_of(lambda: p.encode_pt(X.t(), pt)) == E_SHAPE                        # column-major
+    y = t.zeros(10, dtype=t.float64, device="cuda")
+    assert status_of(lambda: p.encrypt(sk, y, 1, ct)) == E_SHAPE                       # shorter than n
+    assert status_of(lambda: p.decrypt_decode(sk, out, y)) == E_SHAPE                  # fewer than m results
+    assert status_of(lambda: ctx.pt_import(ctx.L, True, t.zeros(2, ctx.N, dtype=t.float64, device="cuda"),
+                                           pt)) == E_INVALID                          # coefficients must be int64

@@ -15,10 +15,11 @@ pytestmark = pytest.mark.gpu
 SEED_SK, SEED_KEYS, SEED_ENC = 11, 12, 13
 
 
-@pytest.fixture(scope="module", params=["C1", "C5"])
+@pytest.fixture(scope="module", params=["C1", "C4", "C5"])
 def c1(request):
-    """a ring-2^12 and a ring-2^15 parameter set (the latter's limbs exceed LDS
-    and take the split transform)"""
+    """a ring-2^12 parameter set; ring 2^14 with three special primes and two
+    digits (C4); ring 2^15, whose limbs exceed LDS and take the split
+    transform"""
     prm = O.Params.from_dict(W.params_dict(request.param))
     ctx = context(request.param)
     sk_gpu = ctx.keygen(SEED_SK)
@@ -357,11 +358,12 @@ def test_row_plan_bit_exact():
     assert np.linalg.norm(z[:m] - X @ y) / np.linalg.norm(X @ y) < 2 ** -20
 
 
-@pytest.mark.parametrize("m,n", [(16, 4), (4, 16), (8, 8)])
-def test_transposed_conversion_bit_exact(m, n):
-    """Eq. 7 (reading): the GPU's [[A^T]] diagonals equal the oracle's residue for residue"""
-    prm = O.Params.from_dict(W.params_dict("C1"))
-    ctx = context("C1")
+@pytest.mark.parametrize("name,m,n", [("C1", 16, 4), ("C1", 4, 16), ("C1", 8, 8), ("C4", 16, 4), ("C4", 4, 16)])
+def test_transposed_conversion_bit_exact(name, m, n):
+    """Eq. 7 (reading): the GPU's [[A^T]] diagonals equal the oracle's residue
+    for residue (C4: three special primes, two digits)"""
+    prm = O.Params.from_dict(W.params_dict(name))
+    ctx = context(name)
     N, S, lv = prm.N, prm.slots, prm.L
     width = max(PL.pow2_ceil(m), PL.pow2_ceil(n))
     rng = np.random.default_rng(m * 3 + n)

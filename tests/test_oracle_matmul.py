@@ -62,6 +62,27 @@ def test_partitioned_hybrid(m, n, logN):
     assert rel_err(run_hybrid(prm, X, y, False, hoisted=False), X @ y) < 1e-3
 
 
+def test_threaded_evaluation_is_the_serial_one():
+    """workers > 1 only spreads independent terms and (output, limb) sums over
+    threads: the residues equal the single-threaded evaluation's, here on a
+    grid case (two row blocks, two column blocks)"""
+    prm = tiny(5, 2, 1)
+    N = prm.N
+    rng = np.random.default_rng(11)
+    X = rng.uniform(-1, 1, (40, 33))
+    y = rng.uniform(-1, 1, 33)
+    plan = PL.HybridPlan(40, 33, prm.slots)
+    assert plan.case == "grid"
+    s = O.keygen(prm, 2)
+    keys = {g: O.rotkey_gen(prm, s, g, 3) for g in PL.hybrid_galois(plan, N)}
+    cts = [O.encrypt(prm, s, m, prm.L, 4 + c) for c, m in enumerate(PL.hybrid_ct_ints(prm, plan, y, prm.scale))]
+    pts = PL.hybrid_pt_ints(prm, plan, X, prm.scale)
+    one = PL.hybrid_matmul(prm, plan, cts, pts, keys, True)
+    many = PL.hybrid_matmul(prm, plan, cts, pts, keys, True, workers=4)
+    for a, b in zip(one, many):
+        assert np.array_equal(a.c0, b.c0) and np.array_equal(a.c1, b.c1)
+
+
 def test_c1_hybrid_unhoisted_precision():
     """C1 with O3 rotations: the rotation order changes the bits, not the
     precision class of the per-rotation ModDown plan."""

@@ -57,6 +57,31 @@ def test_sampler_ranges_and_moments():
     assert O.rand64(9, 7, 7) == w[2] | (w[3] << 32)
 
 
+def test_sampler_mappings_from_raw_words():
+    """Each sample is fixed by its raw 64-bit word u = rand64(seed, stream, i),
+    itself pinned by the published Philox vectors above.  Uniform mod q is the
+    top of the 128-bit product u q: x 2^64 <= u q < (x + 1) 2^64, so samples
+    grow with u (a remainder u mod q would not); ternary splits [0, 2^64)
+    into thirds; CBD(21) is the difference of the bit counts of u's two low
+    21-bit fields.  Checked with exact Python integers on every index."""
+    n = 4096
+    seed, st = 77, O.stream_enc_a(3)
+    words = [O.rand64(seed, st, i) for i in range(n)]
+    for q in (Q40, Q48, 3):
+        x = O.sample_uniform(seed, st, q, n)
+        for u, v in zip(words, x.tolist()):
+            assert v * 2 ** 64 <= u * q < (v + 1) * 2 ** 64
+        order = np.argsort(np.array(words, dtype=np.uint64), kind="stable")
+        assert np.all(np.diff(x[order].astype(np.int64)) >= 0), "uniform samples must grow with the raw word"
+    t = O.sample_ternary(seed, st, n)
+    for u, v in zip(words, t.tolist()):
+        assert (v + 1) * 2 ** 64 <= 3 * u < (v + 2) * 2 ** 64
+    e = O.sample_cbd21(seed, st, n)
+    for u, v in zip(words, e.tolist()):
+        lo, hi = u & (2 ** 21 - 1), (u >> 21) & (2 ** 21 - 1)
+        assert v == bin(lo).count("1") - bin(hi).count("1")
+
+
 # --------------------------------------------------------------------------
 # NTT and negacyclic products
 # --------------------------------------------------------------------------
