@@ -171,6 +171,26 @@ size_t pvfl_bytes_workspace(const pvfl_plan* plan);
 pvfl_status pvfl_matmul_ct_pt(const pvfl_plan* plan, const void* ct_dev, const void* pt_dev, const pvfl_rotkeys* keys,
                               void* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Allocation-free variant of pvfl_matmul_ct_pt, for callers that cannot
+ * allocate device memory while they run: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  It runs the same kernels
+ * with the same results, but its workspace is a fixed array of
+ * pvfl_noalloc_max_bytes() bytes (64 MiB) in device memory, one copy per
+ * device, held until the process ends; the call allocates and frees nothing
+ * and creates no runtime objects (kernel timing is skipped).  The caller
+ * still passes ct_dev, pt_dev and out_dev as for pvfl_matmul_ct_pt.
+ * Every workspace element a call reads was written earlier in the same call,
+ * so the array's previous contents never matter.  All calls on one device
+ * share its array: calls that overlap in time on one device (different
+ * streams, or host threads without ordering) race and must not be issued.
+ * Plans: HYBRID, DIAG with lazy rotate-and-sum, CTMAT and COL.  Errors as
+ * pvfl_matmul_ct_pt, plus PVFL_E_PLAN for ROW and in-ciphertext
+ * rotate-and-sum plans and PVFL_E_SHAPE when the plan's workspace
+ * (pvfl_bytes_workspace) exceeds the array, before anything is enqueued. */
+pvfl_status pvfl_matmul_ct_pt_noalloc(const pvfl_plan* plan, const void* ct_dev, const void* pt_dev,
+                                      const pvfl_rotkeys* keys, void* out_dev, void* stream);
+size_t pvfl_noalloc_max_bytes(void);
+
 /* Real-valued path (canonical-embedding encoding, Sec. 2.2).
  * pvfl_encode_pt: pack the plaintext matrix into the plan's diagonal
  *   plaintexts (Eq. 5 / Eq. 6 layout; for CTMAT the matrix is W, n x n_out)

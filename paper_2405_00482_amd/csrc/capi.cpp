@@ -317,6 +317,7 @@ extern "C" pvfl_status pvfl_context_create(const pvfl_params* prm, int device, p
       ra.inv_last[i] = centred(invm(ql % c->primes[i], c->primes[i]), c->primes[i]);
     }
   }
+  if ((st = noalloc_scratch_init(device)) != PVFL_OK) return st;
   HIP_TRY(hipDeviceSynchronize());
   *out = c.release();
   return PVFL_OK;

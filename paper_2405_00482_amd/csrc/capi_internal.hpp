@@ -101,6 +101,10 @@ struct pvfl_plan {
 };
 
 namespace pvfl {
+// Set by entry points that must not create runtime objects (the
+// allocation-free product): kernel timing is skipped for their launches.
+inline thread_local bool t_timing_off = false;
+
 // Brackets one kernel launch with HIP events when timing is enabled.
 struct KernelTimer {
   pvfl_ctx* c;
@@ -109,7 +113,7 @@ struct KernelTimer {
   double bytes;
   hipEvent_t a = nullptr;
   KernelTimer(pvfl_ctx* c_, void* stream, int cls_, double bytes_) : c(c_), s((hipStream_t)stream), cls(cls_), bytes(bytes_) {
-    if (c->timing_on && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+    if (c->timing_on && !t_timing_off && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
   }
   void stop() {
     if (!a) return;
@@ -127,6 +131,7 @@ LimbMap qp_map(const pvfl_ctx* c, int lv, bool with_p);
 LimbMap key_limb_map(const pvfl_ctx* c, int lv);
 LaunchCtx launch_ctx(const pvfl_ctx* c, void* stream);
 pvfl_status ctx_scratch(pvfl_ctx* c, size_t bytes, double** out);
+pvfl_status noalloc_scratch_init(int device);  // plan.cpp
 pvfl_status keyswitch_digits(pvfl_ctx* c, const pvfl_rotkeys* keys, int lv, const double* digits, int rot_digits,
                              int key_rot, double* u, double* ydown, double* v, void* stream);
 }  // namespace pvfl

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "capi_internal.hpp"
@@ -602,6 +603,74 @@ extern "C" pvfl_status pvfl_matmul_ct_pt(const pvfl_plan* p, const void* ct_v, c
     }
   }
   return fail(PVFL_E_PLAN, "unknown plan kind");
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free product.  Its workspace is a fixed array in device
+// memory: each device the library runs on holds one copy for the life of the
+// process.  In host code `scratch` only names the symbol; the address of a
+// device's copy comes from hipGetSymbolAddress, looked up once per device when
+// a context is created there, and only that address reaches kernels.
+// ---------------------------------------------------------------------------
+static constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kNoAllocDevices] = {};
+
+namespace pvfl {
+// with `device` current (pvfl_context_create)
+pvfl_status noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kNoAllocDevices) return fail(PVFL_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return PVFL_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+  g_scratch_dev[device] = (double*)ptr;
+  return PVFL_OK;
+}
+}  // namespace pvfl
+
+extern "C" size_t pvfl_noalloc_max_bytes(void) { return kNoAllocBytes; }
+
+extern "C" pvfl_status pvfl_matmul_ct_pt_noalloc(const pvfl_plan* p, const void* ct_v, const void* pt_v,
+                                                 const pvfl_rotkeys* keys, void* out_v, void* stream) {
+  if (!p || !ct_v || !pt_v || !out_v) return fail(PVFL_E_INVALID, "null argument");
+  if (p->opts.kind == PVFL_PLAN_ROW || (p->opts.kind == PVFL_PLAN_DIAG && !p->ras_rots.empty()))
+    return fail(PVFL_E_PLAN, "the allocation-free product takes HYBRID, DIAG (lazy rotate-and-sum), CTMAT and COL "
+                             "plans; ROW and in-ciphertext rotate-and-sum run single rotations with their own scratch");
+  const size_t need = ws_doubles(p) * sizeof(double);
+  if (need > kNoAllocBytes)
+    return fail(PVFL_E_SHAPE, "the plan's workspace (" + std::to_string(need) + " bytes) exceeds the " +
+                                  std::to_string(kNoAllocBytes) + "-byte fixed scratch array; use pvfl_matmul_ct_pt");
+  pvfl_status st = check_keys(p, keys);
+  if (st != PVFL_OK) return st;
+  const int dev = p->ctx->device;
+  double* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ws = (dev >= 0 && dev < kNoAllocDevices) ? g_scratch_dev[dev] : nullptr;
+  }
+  if (!ws) return fail(PVFL_E_DEVICE, "no scratch address for the plan's device");
+  const double* ct = (const double*)ct_v;
+  const double* pt = (const double*)pt_v;
+  double* out = (double*)out_v;
+  t_timing_off = true;
+  switch (p->opts.kind) {
+    case PVFL_PLAN_HYBRID:
+    case PVFL_PLAN_DIAG:
+      st = p->opts.lazy_moddown ? run_diag_lazy(p, 1, &ct, &pt, keys, out, ws, stream)
+                                : run_diag_eager(p, ct, pt, keys, out, ws, stream);
+      break;
+    default: {
+      LaunchCtx L = launch_ctx(p->ctx, stream);
+      const hipError_t e = launch_ctmat(L, ct, pt, p->info.ct_in, p->info.ct_out, p->lv, p->ctx->N, out);
+      st = e == hipSuccess ? PVFL_OK : hip_fail(e, "launch_ctmat");
+    }
+  }
+  t_timing_off = false;
+  return st;
 }
 
 // Eq. 4: the terms of one layout summed over Q u P, one ModDown per output

@@ -91,6 +91,7 @@ def lib():
             "pvfl_plan_get_info": [_VP, ctypes.POINTER(PlanInfo)],
             "pvfl_plan_galois": [_VP, ctypes.POINTER(u32), i32],
             "pvfl_matmul_ct_pt": [_VP, _VP, _VP, _VP, _VP, _VP, sz, _VP],
+            "pvfl_matmul_ct_pt_noalloc": [_VP, _VP, _VP, _VP, _VP, _VP],
             "pvfl_pt_import": [_VP, i32, i32, _VP, i32, _VP, _VP],
             "pvfl_encrypt_coeffs": [_VP, _VP, i32, _VP, u64, _VP, _VP],
             "pvfl_export_coeffs": [_VP, i32, i32, _VP, i32, _VP, _VP],
@@ -151,6 +152,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [_VP]
             f.restype = sz
+        L.pvfl_noalloc_max_bytes.argtypes = []
+        L.pvfl_noalloc_max_bytes.restype = sz
         L.pvfl_bytes_workspace_sum.argtypes = [_VP, i32]
         L.pvfl_bytes_workspace_sum.restype = sz
         L.pvfl_mlp_num_params.argtypes = [_VP]
@@ -521,6 +524,19 @@ class Plan(_Handle):
         w = _dev(ws, "workspace", self.bytes("workspace")) if ws is not None else _ptr(None)
         ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
         _check(lib().pvfl_matmul_ct_pt(self.h, c, p, keys.h if keys is not None else None, o, w, ws_bytes, _stream()))
+
+    def matmul_noalloc(self, ct, pt, keys, out):
+        """pvfl_matmul_ct_pt with its workspace in the library's fixed device
+        array: nothing is allocated during the call"""
+        c = _dev(ct, "ciphertexts", self.bytes("ct_in"))
+        p = _dev(pt, "plaintexts", self.bytes("pt"))
+        o = _dev(out, "output", self.bytes("ct_out"))
+        _check(lib().pvfl_matmul_ct_pt_noalloc(self.h, c, p, keys.h if keys is not None else None, o, _stream()))
+
+
+def noalloc_max_bytes() -> int:
+    """size of the fixed scratch array the allocation-free product uses"""
+    return int(lib().pvfl_noalloc_max_bytes())
 
 
 def choose_analytic(ctx: Context, m: int, n: int, costs, level: int = -1, operand: int = 0, n_out: int = 0):
