@@ -33,16 +33,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(name, shapes, n_diag, seeds):
-    """The CPU oracle, untuned, on a bounded sample: the first `n_diag`
-    diagonals of product 0, whole path (encode, encrypt, lazy-ModDown product,
-    decrypt + decode).  Returns cleartext MAC/s of the sample."""
+def _cpu_sample(name, k, shape, n_diag, seeds):
+    """One task of the CPU baseline: product k's first n_diag diagonals on the
+    oracle, whole path (encode the plaintext diagonals, encode and encrypt r,
+    the lazy-ModDown product, decrypt + decode + lazy RaS).  Rotation-key
+    generation is set-up, done before the timer starts.  Returns the
+    cleartext MACs covered (m n D / m') and the timed region's wall-clock
+    start and end."""
     from oracle import oracle as O
     from oracle import plans as PL
     from paper_2405_00482_amd import workloads as W
     prm = O.Params.from_dict(W.params_dict(name))
-    m, n = shapes[0]
-    XT, r = W.c3_inputs(0, shapes[0])
+    m, n = shape
+    XT, r = W.c3_inputs(k, shape)
     plan = PL.HybridPlan(m, n, prm.slots)
     D = min(n_diag, plan.mprime)
 
@@ -53,17 +56,81 @@ def cpu_baseline(name, shapes, n_diag, seeds):
     s = O.keygen(prm, seeds["sk"])
     keys = {O.galois_rotl(i, prm.N): O.rotkey_gen(prm, s, O.galois_rotl(i, prm.N), seeds["rotkeys"])
             for i in range(1, D)}
-    t0 = time.perf_counter()
+    t0 = time.time()
     pts = [O.encode(PL.hybrid_pt_slots(plan, XT, 0, 0, i), prm.N, prm.scale) for i in range(D)]
-    ct = O.encrypt(prm, s, PL.hybrid_ct_ints(prm, plan, r, prm.scale)[0], prm.L, seeds["enc"])
+    ct = O.encrypt(prm, s, PL.hybrid_ct_ints(prm, plan, r, prm.scale)[0], prm.L, seeds["enc"] + k)
     out = PL.hybrid_matmul(prm, Trunc(), [ct], pts, keys, True)[0]
     z = O.decrypt_decode(prm, s, out, prm.scale ** 2)
     PL.hybrid_lazy_ras(plan, [z])
-    dt = time.perf_counter() - t0
-    macs = m * n * D / plan.mprime
-    return {"value": macs / dt, "unit": "MAC/s", "cores": 1, "kind": "oracle",
-            "sample": f"product 0 ({m}x{n}, m'={plan.mprime}): first {D} diagonals, whole path, "
-                      f"{dt:.1f} s single-threaded; rotation-key generation excluded"}
+    t1 = time.time()
+    return m * n * D / plan.mprime, t0, t1
+
+
+def _cpu_worker_ready(_):
+    """load the oracle in a pool worker before the timed tasks"""
+    from oracle import oracle as O
+    O.lib()
+    return os.getpid()
+
+
+def _host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline(name, shapes, seeds, single_tasks=2, single_diag=16, pool_tasks=32, pool_diag=24,
+                 max_workers=16) -> dict:
+    """The CPU oracle as it stands (untuned), timed on the host's cores on a
+    bounded sample of the step: the first diagonals of the first products.
+    * single-thread: products 0..single_tasks-1, first single_diag diagonals
+      each, one after the other in this process;
+    * all cores: products 0..pool_tasks-1, first pool_diag diagonals each, over
+      a process pool of min(max_workers, usable cores) workers; the rate is
+      the MACs of every task over the span from the first task's start to the
+      last one's end.
+    Both rates are cleartext MAC/s of the sample; applied to the whole step
+    they are a per-diagonal extrapolation (every diagonal of a product costs
+    the oracle the same work)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    model, nproc, usable = _host_cpu()
+    macs1, dt1 = 0.0, 0.0
+    for k in range(min(single_tasks, len(shapes))):
+        mk, t0, t1 = _cpu_sample(name, k, shapes[k], single_diag, seeds)
+        macs1 += mk
+        dt1 += t1 - t0
+    workers = max(1, min(max_workers, usable))
+    tasks = list(range(min(pool_tasks, len(shapes))))
+    # spawned workers start from a fresh interpreter (no GPU state is inherited)
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_cpu_worker_ready, range(workers)))   # start and load every worker before timing
+        res = list(ex.map(_cpu_sample, [name] * len(tasks), tasks, [shapes[k] for k in tasks],
+                          [pool_diag] * len(tasks), [seeds] * len(tasks)))
+    macs_all = sum(r[0] for r in res)
+    span = max(r[2] for r in res) - min(r[1] for r in res)
+    step_macs = sum(m * n for (m, n) in shapes)
+    return {"value": macs_all / span, "unit": "MAC/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {pool_diag} diagonals of products 0-{len(tasks) - 1} (whole path, rotation keys "
+                      f"generated beforehand) on {workers} worker processes: {macs_all:.3g} MACs, "
+                      f"{100 * macs_all / step_macs:.1f}% of the step's, in {span:.1f} s; a per-diagonal "
+                      f"extrapolation when applied to the whole step",
+            "single_thread": {"value": macs1 / dt1, "unit": "MAC/s", "cores": 1,
+                              "sample": f"first {single_diag} diagonals of products 0-{single_tasks - 1}: "
+                                        f"{macs1:.3g} MACs in {dt1:.1f} s"},
+            "macs_covered": macs_all, "fraction_of_step_macs": macs_all / step_macs,
+            "cpu_model": model, "nproc": nproc, "usable_cpus": usable, "threads": workers}
 
 
 def ctmat_c4(reps: int = 5) -> dict:
@@ -114,29 +181,42 @@ def ctmat_c4(reps: int = 5) -> dict:
 
 
 def ntt_throughput(ctx, level: int, polys: int = 1024, reps: int = 5) -> dict:
-    """Forward NTTs alone: `polys` signed-integer polynomials imported into
-    every limb of Q u P at `level` (one limb transform per workgroup: read the
-    8N-byte int64 coefficients, reduce, transform, write 8N bytes).  HIP events,
-    median of reps; algorithmic bytes = 16 N per limb transform."""
+    """NTTs alone, both directions, on `polys` polynomials over every limb of
+    Q u P at `level` (one limb transform per workgroup).  HIP events, median of
+    reps.
+    * forward: signed int64 coefficients imported into every limb (reduce,
+      transform); algorithmic bytes = the int64 row once per polynomial plus
+      8N written per limb, 8 N polys (1 + limbs);
+    * inverse: the evaluation-domain limbs exported as canonical uint64
+      coefficients; 8N read and 8N written per limb transform."""
     import torch
     N = ctx.N
     limbs = level + 1 + ctx.alpha
     g = torch.Generator(device="cuda:0").manual_seed(7)
     m = torch.randint(-(1 << 40), 1 << 40, (polys, N), dtype=torch.int64, device="cuda:0", generator=g)
     out = torch.empty(polys * limbs * N, dtype=torch.float64, device="cuda:0")
-    ts = []
-    for _ in range(reps + 1):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        ctx.pt_import(level, True, m, out)
-        e1.record()
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    ms = float(np.median(ts[1:]))
-    nbytes = 16.0 * N * polys * limbs
-    gbps = nbytes / (ms * 1e-3) / 1e9
-    log(f"[bench] NTT: {polys * limbs} limb transforms at N={N} in {ms:.3f} ms, {gbps:.1f} GB/s algorithmic")
-    return {"limb_transforms": polys * limbs, "ms": ms, "algorithmic_GBps": gbps, "frac_of_hbm_peak": gbps / HBM_PEAK_GBS}
+    back = torch.empty(polys * limbs * N, dtype=torch.int64, device="cuda:0")
+
+    def median_ms(fn):
+        ts = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts[1:]))
+
+    ms_f = median_ms(lambda: ctx.pt_import(level, True, m, out))
+    ms_i = median_ms(lambda: ctx.export_coeffs(level, True, out, polys, back))
+    res = {"limb_transforms": polys * limbs}
+    for key, ms, nbytes in (("forward", ms_f, 8.0 * N * polys * (1 + limbs)), ("inverse", ms_i, 16.0 * N * polys * limbs)):
+        gbps = nbytes / (ms * 1e-3) / 1e9
+        res[key] = {"ms": ms, "bytes": nbytes, "algorithmic_GBps": gbps, "frac_of_hbm_peak": gbps / HBM_PEAK_GBS}
+        log(f"[bench] NTT {key}: {polys * limbs} limb transforms at N={N} in {ms:.3f} ms, "
+            f"{gbps:.1f} GB/s algorithmic ({gbps / HBM_PEAK_GBS:.2f} of HBM peak)")
+    return res
 
 
 def copy_calibration(nbytes=256 << 20, reps=3):
@@ -193,7 +273,6 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--products", type=int, default=64)
-    ap.add_argument("--cpu-diagonals", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c4", action="store_true", help="skip the encrypted-matrix (Alg. 3) measurement at C4")
     ap.add_argument("--no-graph", action="store_true")
@@ -252,7 +331,7 @@ def main():
     for k in ("group", "chunk", "vec", "chunk_major"):
         if getattr(args, k) is None:
             setattr(args, k, topts[k])
-    from_db = tuned is not None and all(getattr(args, k) == tuned["opts"][k]
+    from_db = tuned is not None and all(getattr(args, k) == topts[k]
                                        for k in ("group", "chunk", "vec", "chunk_major"))
     log(f"[bench] launch options group {args.group}, chunk {args.chunk}, vec {args.vec}, chunk_major "
         f"{args.chunk_major}{' (tuner database)' if from_db else ''}")
@@ -378,8 +457,11 @@ def main():
         result["c4_ctmat"] = ctmat_c4()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
-        result["cpu_baseline"] = cpu_baseline(name, shapes, args.cpu_diagonals, seeds)
-        log(f"[bench] cpu baseline: {result['cpu_baseline']['value']:.3e} MAC/s")
+        cb = cpu_baseline(name, shapes, seeds)
+        result["cpu_baseline"] = cb
+        log(f"[bench] cpu baseline: {cb['value']:.3e} MAC/s on {cb['cores']} processes "
+            f"({100 * cb['fraction_of_step_macs']:.1f}% of the step's MACs), "
+            f"{cb['single_thread']['value']:.3e} MAC/s single-threaded; {cb['cpu_model']}, nproc {cb['nproc']}")
     print(json.dumps(result), flush=True)
 
 

@@ -144,11 +144,17 @@ void pvfl_pk_destroy(pvfl_pk* pk);
 pvfl_status pvfl_pk_export(const pvfl_pk* pk, uint64_t* out_dev, void* stream);
 
 /* Rotation keys (hybrid key switching) for `count` Galois elements, each a
- * power of 5 modulo 2N (RotL by i slots is 5^i, Sec. 3.1's rotation).  Key
- * memory (count * beta * 2 * (L+1+alpha) * N doubles) is allocated by the
- * library.  Synchronises. */
+ * power of 5 modulo 2N (RotL by i slots is 5^i, Sec. 3.1's rotation).  The
+ * keys live in the caller's device buffer keys_dev (256-byte aligned, at
+ * least pvfl_bytes_rotkeys(ctx, count) bytes): count * beta * 2 * (L+1+alpha)
+ * * N doubles, then a table of N/2 ints mapping a rotation to its key.  The
+ * buffer must stay allocated and unchanged until pvfl_rotkeys_destroy; the
+ * library never frees it.  Repeated elements get one key.  Errors:
+ * PVFL_E_INVALID (element not a power of 5, NULL or misaligned buffer, key of
+ * another context), PVFL_E_SHAPE (buffer too small).  Synchronises. */
+size_t pvfl_bytes_rotkeys(const pvfl_ctx* ctx, int32_t count);
 pvfl_status pvfl_rotkeys_gen(pvfl_ctx* ctx, const pvfl_sk* sk, const uint32_t* galois, int32_t count, uint64_t seed,
-                             pvfl_rotkeys** out);
+                             void* keys_dev, size_t keys_bytes, pvfl_rotkeys** out);
 void pvfl_rotkeys_destroy(pvfl_rotkeys* keys);
 
 /* Plans (Sec. 4 and 5): layout, partitioning, rotation list, op counts. */
@@ -165,9 +171,11 @@ size_t pvfl_bytes_workspace(const pvfl_plan* plan);
 
 /* The hot path.
  * pvfl_matmul_ct_pt: out = the plan's product of the input ciphertexts and
- *   the encoded plaintexts (Alg. 1 loop: sum_i pt_i * HstRotL(ct, i)).  ws may be
- *   NULL (the plan then uses a workspace of its own) or a device buffer of at
- *   least pvfl_bytes_workspace bytes.  Errors: PVFL_E_NOKEY, PVFL_E_SHAPE. */
+ *   the encoded plaintexts (Alg. 1 loop: sum_i pt_i * HstRotL(ct, i)).  ws is
+ *   the caller's device workspace of at least pvfl_bytes_workspace bytes (NULL
+ *   is accepted only by plans that need none: CTMAT, COL).  Errors:
+ *   PVFL_E_NOKEY, PVFL_E_SHAPE (workspace too small), PVFL_E_INVALID (no
+ *   workspace). */
 pvfl_status pvfl_matmul_ct_pt(const pvfl_plan* plan, const void* ct_dev, const void* pt_dev, const pvfl_rotkeys* keys,
                               void* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
@@ -225,7 +233,7 @@ pvfl_status pvfl_encrypt_pk(const pvfl_plan* plan, const pvfl_pk* pk, const doub
  *   ModDown and no baby-step/giant-step split: the terms accumulate over
  *   Q u P and each output ciphertext takes one ModDown.  cts[k], pts[k]:
  *   device buffers of pvfl_bytes_ct_in / pvfl_bytes_pt bytes (host array of
- *   count device pointers); ws: NULL (plan-owned) or at least
+ *   count device pointers); ws: the caller's device workspace of at least
  *   pvfl_bytes_workspace_sum(plan, count) bytes.  Errors: PVFL_E_PLAN for
  *   other plans, PVFL_E_INVALID for count < 1, PVFL_E_NOKEY, PVFL_E_SHAPE.
  * pvfl_encode_out: a cleartext as a plaintext at the plan's output level and
@@ -305,7 +313,10 @@ pvfl_status pvfl_ct_add(pvfl_ctx* ctx, int32_t level, const void* a_dev, const v
  * caller's (arrays of `count` device pointers): X_dev[k] (row stride ldx[k]),
  * v_dev[k] (the encrypted vector), pt_dev[k], ct_dev[k], out_dev[k] sized by
  * the plan queries, y_dev[k] (m_k doubles); X_dev/v_dev/y_dev may be NULL when
- * only pvfl_batch_matmul is used.  The batch owns its workspace.
+ * only pvfl_batch_matmul is used.  So is the workspace ws_dev (256-byte
+ * aligned, at least pvfl_batch_workspace_bytes bytes for the same plans and
+ * options): the batch keeps its launch tables and every intermediate there
+ * and allocates no device memory.  The buffers must outlive the batch.
  * opts (NULL = defaults {2, 32, 1, 1}): see pvfl_batch_opts.
  * pvfl_batch_encrypt: product k uses seed + k.
  * pvfl_batch_run: encode, encrypt, matmul, decrypt in order; with use_graph
@@ -319,10 +330,13 @@ typedef struct {
                            running together share rotation-key lines in L2; 0: product-major */
 } pvfl_batch_opts;
 typedef struct pvfl_batch pvfl_batch;
+pvfl_status pvfl_batch_workspace_bytes(pvfl_ctx* ctx, int32_t count, const pvfl_plan* const* plans,
+                                       const pvfl_batch_opts* opts, size_t* bytes);
 pvfl_status pvfl_batch_create(pvfl_ctx* ctx, int32_t count, const pvfl_plan* const* plans,
                               const double* const* X_dev, const int64_t* ldx, const double* const* v_dev,
                               void* const* pt_dev, void* const* ct_dev, void* const* out_dev, double* const* y_dev,
-                              const pvfl_rotkeys* keys, const pvfl_batch_opts* opts, pvfl_batch** out);
+                              const pvfl_rotkeys* keys, const pvfl_batch_opts* opts, void* ws_dev, size_t ws_bytes,
+                              pvfl_batch** out);
 pvfl_status pvfl_batch_encode(pvfl_batch* batch, void* stream);
 pvfl_status pvfl_batch_encrypt(pvfl_batch* batch, const pvfl_sk* sk, uint64_t seed, void* stream);
 pvfl_status pvfl_batch_matmul(pvfl_batch* batch, void* stream);

@@ -11,6 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpvfl.so")
+PROBE_OUT = os.path.join(HERE, "libpvfl_probe.so")
 SOURCES = ["he_kernels.hip", "encode_kernels.hip", "batch.hip", "mlp.hip", "capi.cpp", "plan.cpp", "codec.cpp",
            "batch.cpp", "mlp_capi.cpp", "planner.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -43,6 +44,10 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, OUT)
+    # the arithmetic-throughput probe (measurement only, its own library)
+    tmp = PROBE_OUT + ".tmp"
+    subprocess.check_call(["hipcc"] + FLAGS + ["-shared", os.path.join(CSRC, "alu_probe.hip"), "-o", tmp])
+    os.replace(tmp, PROBE_OUT)
     return OUT
 
 

@@ -30,7 +30,7 @@ struct pvfl_batch {
   int count = 0, pg = 4, CH = 64, vec = 1, lv = 0, K = 0, beta = 0, max_rows = 0;
   int n_enc_work = 0, n_work = 0, n_slots = 0;
   double inv_scale = 1.0;
-  std::vector<void*> allocs;
+  // every device pointer below lies in the caller's workspace
   BatchProd* prods = nullptr;
   EncodeArgs* args_pt = nullptr;
   EncodeArgs* args_ct = nullptr;
@@ -62,24 +62,177 @@ struct pvfl_batch {
     if (cap_stream2) (void)hipStreamDestroy(cap_stream2);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
-    for (void* p : allocs) (void)hipFree(p);
   }
 };
 
-template <class T>
-static pvfl_status dev_alloc(pvfl_batch* b, size_t count, T** out) {
-  void* p = nullptr;
-  if (hipMalloc(&p, std::max<size_t>(1, count) * sizeof(T)) != hipSuccess) return fail(PVFL_E_NOMEM, "batch allocation");
-  b->allocs.push_back(p);
-  *out = (T*)p;
+namespace {
+
+struct BatchOpts {
+  int group, chunk, vec, order;
+};
+
+pvfl_status read_opts(const pvfl_batch_opts* opts, BatchOpts* o) {
+  const pvfl_batch_opts dflt{2, 32, 1, 1};
+  const pvfl_batch_opts x = opts ? *opts : dflt;
+  if (x.group != 1 && x.group != 2 && x.group != 4) return fail(PVFL_E_INVALID, "group must be 1, 2 or 4");
+  if (x.vec != 1 && x.vec != 2) return fail(PVFL_E_INVALID, "vec must be 1 or 2");
+  if (x.chunk > 1024) return fail(PVFL_E_INVALID, "chunk must be at most 1024");
+  if (x.chunk < 1) return fail(PVFL_E_INVALID, "chunk must be positive");
+  *o = BatchOpts{x.group, x.chunk, x.vec, x.chunk_major};
   return PVFL_OK;
 }
+
+// the plans a batch accepts: lazy, hoisted HYBRID (or DIAG without in-ciphertext
+// RaS) plans of one context, level and plaintext scale, one input and one output
+pvfl_status check_plans(pvfl_ctx* c, int count, const pvfl_plan* const* plans) {
+  if (!c || !plans || count < 1) return fail(PVFL_E_INVALID, "bad argument");
+  const pvfl_plan* p0 = plans[0];
+  if (!p0) return fail(PVFL_E_INVALID, "null plan");
+  if (p0->beta > 4) return fail(PVFL_E_PLAN, "batched kernel supports up to 4 digits");
+  for (int k = 0; k < count; ++k) {
+    const pvfl_plan* p = plans[k];
+    if (!p || p->ctx != c) return fail(PVFL_E_INVALID, "plan belongs to another context");
+    const bool ok_kind = p->opts.kind == PVFL_PLAN_HYBRID || (p->opts.kind == PVFL_PLAN_DIAG && p->ras_rots.empty());
+    if (!ok_kind || !p->opts.lazy_moddown || p->info.ct_in != 1 || p->info.ct_out != 1 || p->info.bsgs != 0)
+      return fail(PVFL_E_PLAN, "batched products must be lazy, hoisted HYBRID/DIAG plans with one input and one "
+                               "output ciphertext");
+    if (p->lv != p0->lv) return fail(PVFL_E_LEVEL, "batched products must share the level");
+    if (p->pt_scale != p0->pt_scale) return fail(PVFL_E_PLAN, "batched products must share the plaintext scale");
+  }
+  return PVFL_OK;
+}
+
+// Work schedule of the fused kernel: groups of products with similar m'
+// (descending), chunked diagonal ranges, and the task list of workgroups.
+struct Schedule {
+  std::vector<DiagGroup> groups;
+  std::vector<DiagWork> work;
+  std::vector<DiagTask> tasks;
+  std::vector<int> part0;  // first partial-sum slot of each product
+  int n_slots = 0;
+  double key_reads = 0;    // rotation keys streamed (once per group and diagonal)
+  int max_mp = 0;
+};
+
+Schedule make_schedule(const std::vector<int>& mprime, int K, int N, const BatchOpts& o) {
+  Schedule S;
+  const int count = (int)mprime.size();
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int z) { return mprime[a] > mprime[z]; });
+  for (int g0 = 0; g0 < count; g0 += o.group) {
+    DiagGroup G{};
+    G.np = std::min(o.group, count - g0);
+    int mx = 0;
+    for (int u = 0; u < G.np; ++u) {
+      G.prod[u] = order[g0 + u];
+      mx = std::max(mx, mprime[G.prod[u]]);
+    }
+    for (int i0 = 0; i0 < mx; i0 += o.chunk)
+      S.work.push_back(DiagWork{(int)S.groups.size(), i0, std::min(i0 + o.chunk, mx), 0});
+    S.key_reads += std::max(0, mx - 1);
+    S.groups.push_back(G);
+    S.max_mp = std::max(S.max_mp, mx);
+  }
+  // Chunk-major order: work items of every group for diagonals [0, CH) first,
+  // then [CH, 2 CH), ...  Blocks are dispatched round-robin over the 8 XCDs by
+  // linear block index; the blocks of one (tile, limb) for consecutive work
+  // items are (N/256)*K apart, a multiple of 8, so they land on the same XCD
+  // and read the same rotation-key lines from its L2.
+  if (o.order == 1)
+    std::stable_sort(S.work.begin(), S.work.end(), [](const DiagWork& a, const DiagWork& z) { return a.i0 < z.i0; });
+  // task list: for each chunk (in order), tile, limb: the work items of that
+  // chunk, so that consecutive tasks read the same rotation-key tile
+  const int ntile = N / (256 * o.vec);
+  size_t w0 = 0;
+  while (w0 < S.work.size()) {
+    size_t w1 = w0;
+    while (w1 < S.work.size() && S.work[w1].i0 == S.work[w0].i0) ++w1;
+    if (o.order != 1) w1 = w0 + 1;
+    for (int tile = 0; tile < ntile; ++tile)
+      for (int r = 0; r < K; ++r)
+        for (size_t wi = w0; wi < w1; ++wi) S.tasks.push_back(DiagTask{(int)wi, tile, r, 0});
+    w0 = w1;
+  }
+  S.part0.resize(count);
+  for (int k = 0; k < count; ++k) {
+    S.part0[k] = S.n_slots;
+    S.n_slots += (mprime[k] + o.chunk - 1) / o.chunk;
+  }
+  return S;
+}
+
+// Byte offsets of everything a batch keeps in device memory, carved from one
+// workspace in this order (each piece 256-byte aligned): the tables of the
+// launches, then the buffers of the phases.
+struct Layout {
+  size_t prods, args_pt, args_ct, enc_work, groups, work, tasks, ct_tab, ct_out_tab, out_tab;
+  size_t digits, yup, pc, part, acc, ydown, msg, res, z;
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    const size_t o = total;
+    total += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+Layout make_layout(const pvfl_ctx* c, int count, int n_enc_work, const Schedule& S, int lv, int K, int beta) {
+  const size_t N = c->N, KN = (size_t)K * N, Q = (size_t)(lv + 1) * N, cn = (size_t)count;
+  Layout L{};
+  L.prods = L.take(sizeof(BatchProd) * cn);
+  L.args_pt = L.take(sizeof(EncodeArgs) * cn);
+  L.args_ct = L.take(sizeof(EncodeArgs) * cn);
+  L.enc_work = L.take(sizeof(int2) * (size_t)n_enc_work);
+  L.groups = L.take(sizeof(DiagGroup) * S.groups.size());
+  L.work = L.take(sizeof(DiagWork) * S.work.size());
+  L.tasks = L.take(sizeof(DiagTask) * S.tasks.size());
+  L.ct_tab = L.take(sizeof(double*) * cn);
+  L.ct_out_tab = L.take(sizeof(double*) * cn);
+  L.out_tab = L.take(sizeof(double*) * cn);
+  L.digits = L.take(sizeof(double) * cn * beta * KN);
+  L.yup = L.take(sizeof(double) * cn * Q);
+  L.pc = L.take(sizeof(double) * cn * 2 * Q);
+  L.part = L.take(sizeof(double) * (size_t)S.n_slots * 2 * KN);
+  L.acc = L.take(sizeof(double) * cn * 2 * KN);
+  L.ydown = L.take(sizeof(double) * cn * 2 * c->alpha * N);
+  L.msg = L.take(sizeof(int64_t) * cn * N);
+  L.res = L.take(sizeof(double) * cn * Q);
+  L.z = L.take(sizeof(double) * cn * (N / 2));
+  return L;
+}
+
 template <class T>
-static pvfl_status dev_put(pvfl_batch* b, const std::vector<T>& v, T** out) {
-  pvfl_status st = dev_alloc(b, v.size(), out);
+pvfl_status upload(const std::vector<T>& v, char* base, size_t off) {
+  if (v.empty()) return PVFL_OK;
+  const hipError_t e = hipMemcpy(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e == hipSuccess ? PVFL_OK : hip_fail(e, "batch table upload");
+}
+
+int total_pts(int count, const pvfl_plan* const* plans) {
+  int n = 0;
+  for (int k = 0; k < count; ++k) n += plans[k]->info.n_pts;
+  return n;
+}
+
+std::vector<int> mprimes_of(int count, const pvfl_plan* const* plans) {
+  std::vector<int> mp(count);
+  for (int k = 0; k < count; ++k) mp[k] = plans[k]->info.mprime;
+  return mp;
+}
+
+}  // namespace
+
+extern "C" pvfl_status pvfl_batch_workspace_bytes(pvfl_ctx* c, int32_t count, const pvfl_plan* const* plans,
+                                                  const pvfl_batch_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(PVFL_E_INVALID, "null argument");
+  *bytes = 0;
+  BatchOpts o;
+  pvfl_status st = read_opts(opts, &o);
   if (st != PVFL_OK) return st;
-  if (!v.empty() && hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
-    return fail(PVFL_E_DEVICE, "batch table upload");
+  if ((st = check_plans(c, count, plans)) != PVFL_OK) return st;
+  const pvfl_plan* p0 = plans[0];
+  const Schedule S = make_schedule(mprimes_of(count, plans), p0->K, c->N, o);
+  *bytes = make_layout(c, count, total_pts(count, plans), S, p0->lv, p0->K, p0->beta).total;
   return PVFL_OK;
 }
 
@@ -87,29 +240,25 @@ extern "C" pvfl_status pvfl_batch_create(pvfl_ctx* c, int32_t count, const pvfl_
                                          const double* const* X_dev, const int64_t* ldx, const double* const* v_dev,
                                          void* const* pt_dev, void* const* ct_dev, void* const* out_dev,
                                          double* const* y_dev, const pvfl_rotkeys* keys, const pvfl_batch_opts* opts,
-                                         pvfl_batch** out) {
-  const pvfl_batch_opts dflt{2, 32, 1, 1};
-  const pvfl_batch_opts o = opts ? *opts : dflt;
-  int group = o.group, chunk = o.chunk;
-  const int vec = o.vec, order_mode = o.chunk_major;
-  if (!c || !plans || !pt_dev || !ct_dev || !out_dev || !out || count < 1) return fail(PVFL_E_INVALID, "bad argument");
+                                         void* ws_dev, size_t ws_bytes, pvfl_batch** out) {
+  if (!out) return fail(PVFL_E_INVALID, "bad argument");
   *out = nullptr;
-  if (group != 1 && group != 2 && group != 4) return fail(PVFL_E_INVALID, "group must be 1, 2 or 4");
-  if (vec != 1 && vec != 2) return fail(PVFL_E_INVALID, "vec must be 1 or 2");
-  if (chunk > 1024) return fail(PVFL_E_INVALID, "chunk must be at most 1024");
-  if (chunk < 1) return fail(PVFL_E_INVALID, "chunk must be positive");
+  if (!pt_dev || !ct_dev || !out_dev) return fail(PVFL_E_INVALID, "bad argument");
+  BatchOpts o;
+  pvfl_status st = read_opts(opts, &o);
+  if (st != PVFL_OK) return st;
+  if ((st = check_plans(c, count, plans)) != PVFL_OK) return st;
   std::unique_ptr<pvfl_batch> b(new pvfl_batch());
   b->ctx = c;
   b->keys = keys;
   b->count = count;
-  b->pg = group;
-  b->vec = vec;
-  b->CH = chunk;
+  b->pg = o.group;
+  b->vec = o.vec;
+  b->CH = o.chunk;
   const pvfl_plan* p0 = plans[0];
   b->lv = p0->lv;
   b->K = p0->K;
   b->beta = p0->beta;
-  if (b->beta > 4) return fail(PVFL_E_PLAN, "batched kernel supports up to 4 digits");
   const int N = c->N;
   std::vector<BatchProd> prods(count);
   std::vector<EncodeArgs> apt(count), act(count);
@@ -118,18 +267,13 @@ extern "C" pvfl_status pvfl_batch_create(pvfl_ctx* c, int32_t count, const pvfl_
   std::vector<double*> ct_out_tab(count), out_tab(count);
   for (int k = 0; k < count; ++k) {
     const pvfl_plan* p = plans[k];
-    if (!p || p->ctx != c) return fail(PVFL_E_INVALID, "plan belongs to another context");
-    const bool ok_kind = p->opts.kind == PVFL_PLAN_HYBRID || (p->opts.kind == PVFL_PLAN_DIAG && p->ras_rots.empty());
-    if (!ok_kind || !p->opts.lazy_moddown || p->info.ct_in != 1 || p->info.ct_out != 1 || p->info.bsgs != 0)
-      return fail(PVFL_E_PLAN, "batched products must be lazy, hoisted HYBRID/DIAG plans with one input and one "
-                               "output ciphertext");
-    if (p->lv != b->lv) return fail(PVFL_E_LEVEL, "batched products must share the level");
-    if (p->pt_scale != p0->pt_scale) return fail(PVFL_E_PLAN, "batched products must share the plaintext scale");
     if (!p->galois.empty()) {
       if (!keys || keys->ctx != c) return fail(PVFL_E_NOKEY, "batch needs rotation keys");
       for (uint32_t g : p->galois)
         if (keys->slot_of_rot[c->log5[g]] < 0) return fail(PVFL_E_NOKEY, "missing rotation key");
     }
+    if ((X_dev && !X_dev[k]) || (v_dev && !v_dev[k]) || (y_dev && !y_dev[k]) || !pt_dev[k] || !ct_dev[k] || !out_dev[k])
+      return fail(PVFL_E_INVALID, "null buffer for product " + std::to_string(k));
     if (X_dev && ldx && ldx[k] < p->info.n)
       return fail(PVFL_E_SHAPE, "product " + std::to_string(k) + ": leading dimension smaller than the row length");
     BatchProd& B = prods[k];
@@ -155,89 +299,51 @@ extern "C" pvfl_status pvfl_batch_create(pvfl_ctx* c, int32_t count, const pvfl_
   b->has_X = X_dev != nullptr;
   b->has_v = v_dev != nullptr;
   b->has_y = y_dev != nullptr;
-  for (int k = 0; k < count; ++k) {
-    if ((X_dev && !X_dev[k]) || (v_dev && !v_dev[k]) || (y_dev && !y_dev[k]) || !pt_dev[k] || !ct_dev[k] || !out_dev[k])
-      return fail(PVFL_E_INVALID, "null buffer for product " + std::to_string(k));
-  }
-  // groups of products with similar m' (descending), chunked diagonal ranges
-  std::vector<int> order(count);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int z) { return prods[a].mprime > prods[z].mprime; });
-  std::vector<DiagGroup> groups;
-  std::vector<DiagWork> work;
-  double key_reads = 0;
-  for (int g0 = 0; g0 < count; g0 += group) {
-    DiagGroup G{};
-    G.np = std::min(group, count - g0);
-    int mx = 0;
-    for (int u = 0; u < G.np; ++u) {
-      G.prod[u] = order[g0 + u];
-      mx = std::max(mx, prods[G.prod[u]].mprime);
-    }
-    for (int i0 = 0; i0 < mx; i0 += chunk) work.push_back(DiagWork{(int)groups.size(), i0, std::min(i0 + chunk, mx), 0});
-    key_reads += std::max(0, mx - 1);
-    groups.push_back(G);
-  }
-  b->key_bytes = key_reads * 8.0 * 2 * b->beta * b->K * N;
+  const Schedule S = make_schedule(mprimes_of(count, plans), b->K, N, o);
+  for (int k = 0; k < count; ++k) prods[k].part0 = S.part0[k];
+  b->key_bytes = S.key_reads * 8.0 * 2 * b->beta * b->K * N;
   // algorithmic minimum: every distinct rotation key of the batch streamed once
-  {
-    int max_mp = 0;
-    for (int k = 0; k < count; ++k) max_mp = std::max(max_mp, prods[k].mprime);
-    b->key_bytes_min = std::max(0, max_mp - 1) * 8.0 * 2 * b->beta * b->K * N;
-  }
-  // Chunk-major order: work items of every group for diagonals [0, CH) first,
-  // then [CH, 2 CH), ...  Blocks are dispatched round-robin over the 8 XCDs by
-  // linear block index; the blocks of one (tile, limb) for consecutive work
-  // items are (N/256)*K apart, a multiple of 8, so they land on the same XCD
-  // and read the same rotation-key lines from its L2.
-  if (order_mode == 1)
-    std::stable_sort(work.begin(), work.end(), [](const DiagWork& a, const DiagWork& z) { return a.i0 < z.i0; });
-  // task list: for each chunk (in order), tile, limb: the work items of that
-  // chunk, so that consecutive tasks read the same rotation-key tile
-  std::vector<DiagTask> tasks;
-  {
-    const int ntile = N / (256 * vec);
-    size_t w0 = 0;
-    while (w0 < work.size()) {
-      size_t w1 = w0;
-      while (w1 < work.size() && work[w1].i0 == work[w0].i0) ++w1;
-      if (order_mode != 1) w1 = w0 + 1;
-      for (int tile = 0; tile < ntile; ++tile)
-        for (int r = 0; r < b->K; ++r)
-          for (size_t wi = w0; wi < w1; ++wi) tasks.push_back(DiagTask{(int)wi, tile, r, 0});
-      w0 = w1;
-    }
-  }
-  b->n_tasks = (int)tasks.size();
-  int slot = 0;
-  for (int k = 0; k < count; ++k) {
-    prods[k].part0 = slot;
-    slot += (prods[k].mprime + chunk - 1) / chunk;
-  }
-  b->n_slots = slot;
-  b->n_work = (int)work.size();
+  b->key_bytes_min = std::max(0, S.max_mp - 1) * 8.0 * 2 * b->beta * b->K * N;
+  b->n_tasks = (int)S.tasks.size();
+  b->n_slots = S.n_slots;
+  b->n_work = (int)S.work.size();
   b->n_enc_work = (int)encw.size();
-  pvfl_status st;
-  if ((st = dev_put(b.get(), prods, &b->prods)) != PVFL_OK) return st;
-  if ((st = dev_put(b.get(), apt, &b->args_pt)) != PVFL_OK) return st;
-  if ((st = dev_put(b.get(), act, &b->args_ct)) != PVFL_OK) return st;
-  if ((st = dev_put(b.get(), encw, &b->enc_work)) != PVFL_OK) return st;
-  if ((st = dev_put(b.get(), groups, &b->groups)) != PVFL_OK) return st;
-  if ((st = dev_put(b.get(), work, &b->work)) != PVFL_OK) return st;
-  if ((st = dev_put(b.get(), tasks, &b->tasks)) != PVFL_OK) return st;
-  if ((st = dev_put(b.get(), ct_tab, &b->ct_tab)) != PVFL_OK) return st;
-  if ((st = dev_put(b.get(), ct_out_tab, &b->ct_out_tab)) != PVFL_OK) return st;
-  if ((st = dev_put(b.get(), out_tab, &b->out_tab)) != PVFL_OK) return st;
-  const size_t KN = (size_t)b->K * N, Q = (size_t)(b->lv + 1) * N;
-  if ((st = dev_alloc(b.get(), (size_t)count * b->beta * KN, &b->digits)) != PVFL_OK) return st;
-  if ((st = dev_alloc(b.get(), (size_t)count * Q, &b->yup)) != PVFL_OK) return st;
-  if ((st = dev_alloc(b.get(), (size_t)count * 2 * Q, &b->pc)) != PVFL_OK) return st;
-  if ((st = dev_alloc(b.get(), (size_t)slot * 2 * KN, &b->part)) != PVFL_OK) return st;
-  if ((st = dev_alloc(b.get(), (size_t)count * 2 * KN, &b->acc)) != PVFL_OK) return st;
-  if ((st = dev_alloc(b.get(), (size_t)count * 2 * c->alpha * N, &b->ydown)) != PVFL_OK) return st;
-  if ((st = dev_alloc(b.get(), (size_t)count * N, &b->msg)) != PVFL_OK) return st;
-  if ((st = dev_alloc(b.get(), (size_t)count * Q, &b->res)) != PVFL_OK) return st;
-  if ((st = dev_alloc(b.get(), (size_t)count * (N / 2), &b->z)) != PVFL_OK) return st;
+  const Layout L = make_layout(c, count, b->n_enc_work, S, b->lv, b->K, b->beta);
+  if (!ws_dev) return fail(PVFL_E_INVALID, "the batch needs a workspace of pvfl_batch_workspace_bytes bytes");
+  if (ws_bytes < L.total)
+    return fail(PVFL_E_SHAPE, "workspace of " + std::to_string(ws_bytes) + " bytes, the batch needs " +
+                                  std::to_string(L.total));
+  if (((uintptr_t)ws_dev & 255) != 0) return fail(PVFL_E_INVALID, "the workspace must be 256-byte aligned");
+  char* base = (char*)ws_dev;
+  if ((st = upload(prods, base, L.prods)) != PVFL_OK) return st;
+  if ((st = upload(apt, base, L.args_pt)) != PVFL_OK) return st;
+  if ((st = upload(act, base, L.args_ct)) != PVFL_OK) return st;
+  if ((st = upload(encw, base, L.enc_work)) != PVFL_OK) return st;
+  if ((st = upload(S.groups, base, L.groups)) != PVFL_OK) return st;
+  if ((st = upload(S.work, base, L.work)) != PVFL_OK) return st;
+  if ((st = upload(S.tasks, base, L.tasks)) != PVFL_OK) return st;
+  if ((st = upload(ct_tab, base, L.ct_tab)) != PVFL_OK) return st;
+  if ((st = upload(ct_out_tab, base, L.ct_out_tab)) != PVFL_OK) return st;
+  if ((st = upload(out_tab, base, L.out_tab)) != PVFL_OK) return st;
+  b->prods = (BatchProd*)(base + L.prods);
+  b->args_pt = (EncodeArgs*)(base + L.args_pt);
+  b->args_ct = (EncodeArgs*)(base + L.args_ct);
+  b->enc_work = (int2*)(base + L.enc_work);
+  b->groups = (DiagGroup*)(base + L.groups);
+  b->work = (DiagWork*)(base + L.work);
+  b->tasks = (DiagTask*)(base + L.tasks);
+  b->ct_tab = (const double**)(base + L.ct_tab);
+  b->ct_out_tab = (double**)(base + L.ct_out_tab);
+  b->out_tab = (double**)(base + L.out_tab);
+  b->digits = (double*)(base + L.digits);
+  b->yup = (double*)(base + L.yup);
+  b->pc = (double*)(base + L.pc);
+  b->part = (double*)(base + L.part);
+  b->acc = (double*)(base + L.acc);
+  b->ydown = (double*)(base + L.ydown);
+  b->msg = (int64_t*)(base + L.msg);
+  b->res = (double*)(base + L.res);
+  b->z = (double*)(base + L.z);
   *out = b.release();
   return PVFL_OK;
 }
@@ -323,9 +429,10 @@ static pvfl_status batch_product(pvfl_batch* b, void* stream) {
   a.part = b->part;
   {
     // algorithmic bytes: each distinct rotation key once, every plaintext once, digits and P*c once,
-    // partial sums written once
+    // and each product's 2K-limb accumulator written once (the chunk partial sums the kernel
+    // writes instead are an intermediate of this kernel's own design, not counted)
     const double bytes = b->key_bytes_min + b->pt_bytes + 8.0 * (double)b->count * ((size_t)b->beta * KN + 2 * Q) +
-                         8.0 * (double)b->n_slots * 2 * KN;
+                         8.0 * (double)b->count * 2 * KN;
     KernelTimer kt(c, stream, PVFL_TIMING_DIAG, bytes);
     HIP_TRY(launch_diag_batch(L, a, b->pg, b->beta, b->vec));
     kt.stop();

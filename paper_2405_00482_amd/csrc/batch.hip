@@ -26,6 +26,7 @@ namespace pvfl {
 // ---------------------------------------------------------------------------
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
+
 template <int PG, int BETA, int V>
 __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
   extern __shared__ double stage[];  // [PG][BETA + 1][win]
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
       const double* src = (j < BETA) ? dig + (size_t)j * KN : pc;
       double* dst = stage + (size_t)(p * (BETA + 1) + j) * win;
       for (int x = threadIdx.x; x < span; x += 256)  // read once per task: streamed past L2 as well
-        dst[spos(x)] = __builtin_nontemporal_load(src + ((t0 & half) | ((t0 + w.i0 + x) & (half - 1))));
+        dst[spos(x)] = __builtin_nontemporal_load(gmem(src) + ((t0 & half) | ((t0 + w.i0 + x) & (half - 1))));
     }
   }
   __syncthreads();
@@ -101,9 +102,9 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
         const double* pcs = stage + (size_t)(p * (BETA + 1) + BETA) * win;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          const double pv = ptp[p][v];
+          const double pv = gmem(ptp[p])[v];
           acc0[p][v] += mulmod(pv, pcs[spos(tl + v)], m);
-          acc1[p][v] += mulmod(pv, a.pc[(size_t)G.prod[p] * a.pc_stride + Qoff + limbN + t0 + tl + v], m);
+          acc1[p][v] += mulmod(pv, gmem(a.pc)[(size_t)G.prod[p] * a.pc_stride + Qoff + limbN + t0 + tl + v], m);
         }
       }
     }
@@ -111,13 +112,17 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
     ++cnt;
   }
   // key limbs (b_j, a_j) of rotation i at this thread's V indices
-  auto load_keys = [&](int ii, double (&kb)[BETA][V], double (&ka)[BETA][V]) {
-    const double* key = a.keys + (size_t)a.slot_of_rot[ii] * a.key_stride + (size_t)klimb * N + t0 + tl;
+  // the key of rotation ii sits at slot slot_of_rot[ii] of the key set; the
+  // loops read those slots one step ahead, so that no scalar-load wait stands
+  // between a step's compute and the next step's loads
+  auto slot_of = [&](int ii) { return a.slot_of_rot[min(ii, w.i1 - 1)]; };
+  auto load_keys = [&](int slot, double (&kb)[BETA][V], double (&ka)[BETA][V]) {
+    const auto* key = gmem(a.keys) + (size_t)slot * a.key_stride + (size_t)klimb * N + t0 + tl;
 #pragma unroll
     for (int j = 0; j < BETA; ++j) {
       if (V == 2) {
-        const double2 b2 = *(const double2*)(key + (size_t)j * 2 * a.key_limbs * N);
-        const double2 a2 = *(const double2*)(key + (size_t)(j * 2 + 1) * a.key_limbs * N);
+        const dbl2 b2 = *(const __attribute__((address_space(1))) dbl2*)(key + (size_t)j * 2 * a.key_limbs * N);
+        const dbl2 a2 = *(const __attribute__((address_space(1))) dbl2*)(key + (size_t)(j * 2 + 1) * a.key_limbs * N);
         kb[j][0] = b2.x; kb[j][V - 1] = b2.y;
         ka[j][0] = a2.x; ka[j][V - 1] = a2.y;
       } else {
@@ -138,11 +143,11 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
       const bool has = p < np && ii < mp[p];
       const double* src = ptp[p < np ? p : 0] + (size_t)(has ? ii : 0) * KN;
       if (V == 2) {
-        const dbl2 p2 = __builtin_nontemporal_load((const dbl2*)src);
+        const dbl2 p2 = __builtin_nontemporal_load(gmem((const dbl2*)src));
         pv[p][0] = has ? p2.x : 0.0;
         pv[p][V - 1] = has ? p2.y : 0.0;
       } else {
-        const double x = __builtin_nontemporal_load(src);
+        const double x = __builtin_nontemporal_load(gmem(src));
         pv[p][0] = has ? x : 0.0;
       }
     }
@@ -183,16 +188,20 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
       cnt = 0;
     }
   };
+  // (a chunk with no rotated diagonal may come with no key set at all)
+  int sl0 = i < w.i1 ? slot_of(i) : 0, sl1 = i + 1 < w.i1 ? slot_of(i + 1) : 0;
   // two diagonals per step: both diagonals' key and plaintext loads are
   // issued before either is used, which doubles the memory requests each
   // wave has in flight (the LDS stage already limits occupancy to three
   // waves per SIMD, which leaves the registers for this)
   for (; i + 1 < w.i1; i += 2) {
     double kb0[BETA][V], ka0[BETA][V], kb1[BETA][V], ka1[BETA][V], pv0[PG][V], pv1[PG][V];
-    load_keys(i, kb0, ka0);
+    load_keys(sl0, kb0, ka0);
     load_pt(i, pv0);
-    load_keys(i + 1, kb1, ka1);
+    load_keys(sl1, kb1, ka1);
     load_pt(i + 1, pv1);
+    sl0 = slot_of(i + 2);
+    sl1 = slot_of(i + 3);
     apply(i, kb0, ka0, pv0);
     apply(i + 1, kb1, ka1, pv1);
     cnt += 2;
@@ -200,7 +209,7 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
   }
   if (i < w.i1) {
     double kb0[BETA][V], ka0[BETA][V], pv0[PG][V];
-    load_keys(i, kb0, ka0);
+    load_keys(sl0, kb0, ka0);
     load_pt(i, pv0);
     apply(i, kb0, ka0, pv0);
   }
@@ -237,12 +246,12 @@ __global__ __launch_bounds__(256) void k_sum_partials_batch(const double* __rest
   for (; c + 8 <= nch; c += 8) {
     double t[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = __builtin_nontemporal_load(src + (size_t)(c + u) * tot);
+    for (int u = 0; u < 8; ++u) t[u] = __builtin_nontemporal_load(gmem(src) + (size_t)(c + u) * tot);
 #pragma unroll
     for (int u = 0; u < 8; ++u) v += t[u];
     v = reduce(v, m);
   }
-  for (; c < nch; ++c) v += __builtin_nontemporal_load(src + (size_t)c * tot);
+  for (; c < nch; ++c) v += __builtin_nontemporal_load(gmem(src) + (size_t)c * tot);
   acc[(size_t)p * tot + idx] = reduce(v, m);
 }
 

@@ -331,10 +331,7 @@ extern "C" void pvfl_context_destroy(pvfl_ctx* c) { delete c; }
 pvfl_sk::~pvfl_sk() {
   if (s) (void)hipFree(s);
 }
-pvfl_rotkeys::~pvfl_rotkeys() {
-  if (keys) (void)hipFree(keys);
-  if (slot_of_rot_dev) (void)hipFree(slot_of_rot_dev);
-}
+pvfl_rotkeys::~pvfl_rotkeys() {}  // the key memory is the caller's
 
 extern "C" pvfl_status pvfl_keygen(pvfl_ctx* c, uint64_t seed, pvfl_sk** out) {
   if (!c || !out) return fail(PVFL_E_INVALID, "null argument");
@@ -374,15 +371,31 @@ extern "C" pvfl_status pvfl_pk_export(const pvfl_pk* pk, uint64_t* out, void* st
   return PVFL_OK;
 }
 
+// Key memory: [count][beta][2][L+1+alpha][N] doubles, then the rotation ->
+// key-index table (N/2 ints), 256-byte aligned.
+static size_t rotkey_stride(const pvfl_ctx* c) {
+  const int beta = (c->n_q + c->alpha - 1) / c->alpha;
+  return (size_t)beta * 2 * c->primes.size() * c->N;
+}
+static size_t rotkey_table_off(const pvfl_ctx* c, int count) {
+  return ((sizeof(double) * rotkey_stride(c) * (size_t)std::max(count, 0)) + 255) & ~(size_t)255;
+}
+extern "C" size_t pvfl_bytes_rotkeys(const pvfl_ctx* c, int32_t count) {
+  if (!c || count < 0) return 0;
+  return rotkey_table_off(c, count) + sizeof(int) * (size_t)(c->N / 2);
+}
+
 extern "C" pvfl_status pvfl_rotkeys_gen(pvfl_ctx* c, const pvfl_sk* sk, const uint32_t* galois, int32_t count,
-                                        uint64_t seed, pvfl_rotkeys** out) {
+                                        uint64_t seed, void* keys_dev, size_t keys_bytes, pvfl_rotkeys** out) {
   if (!c || !sk || !out || (count > 0 && !galois) || count < 0) return fail(PVFL_E_INVALID, "bad argument");
+  *out = nullptr;
+  if (sk->ctx != c) return fail(PVFL_E_INVALID, "secret key belongs to another context");
   std::unique_ptr<pvfl_rotkeys> rk(new pvfl_rotkeys());
   rk->ctx = c;
   const int N = c->N;
   rk->key_limbs = (int)c->primes.size();
   rk->beta = (c->n_q + c->alpha - 1) / c->alpha;
-  rk->key_stride = (size_t)rk->beta * 2 * rk->key_limbs * N;
+  rk->key_stride = rotkey_stride(c);
   rk->slot_of_rot.assign(N / 2, -1);
   for (int k = 0; k < count; ++k) {
     const uint32_t g = galois[k];
@@ -395,10 +408,15 @@ extern "C" pvfl_status pvfl_rotkeys_gen(pvfl_ctx* c, const pvfl_sk* sk, const ui
     rk->rot.push_back(rot);
   }
   const int nk = (int)rk->galois.size();
-  const size_t bytes = sizeof(double) * rk->key_stride * std::max(nk, 1);
-  if (hipMalloc((void**)&rk->keys, bytes) != hipSuccess) return fail(PVFL_E_NOMEM, "rotation key allocation");
-  if (hipMalloc((void**)&rk->slot_of_rot_dev, sizeof(int) * (N / 2)) != hipSuccess)
-    return fail(PVFL_E_NOMEM, "rotation key table allocation");
+  const size_t need = pvfl_bytes_rotkeys(c, nk);
+  if (!keys_dev) return fail(PVFL_E_INVALID, "the keys need a device buffer of pvfl_bytes_rotkeys bytes");
+  if (keys_bytes < need)
+    return fail(PVFL_E_SHAPE, "key buffer of " + std::to_string(keys_bytes) + " bytes, the keys need " +
+                                  std::to_string(need));
+  if (((uintptr_t)keys_dev & 255) != 0) return fail(PVFL_E_INVALID, "the key buffer must be 256-byte aligned");
+  rk->keys = (double*)keys_dev;
+  rk->slot_of_rot_dev = (int*)((char*)keys_dev + rotkey_table_off(c, nk));
+  HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(hipMemcpy(rk->slot_of_rot_dev, rk->slot_of_rot.data(), sizeof(int) * (N / 2), hipMemcpyHostToDevice));
   RotKeyArgs ka{};
   ka.n_limbs = rk->key_limbs;
@@ -411,24 +429,18 @@ extern "C" pvfl_status pvfl_rotkeys_gen(pvfl_ctx* c, const pvfl_sk* sk, const ui
     for (int k = 0; k < c->alpha; ++k) pm = mulm(pm, c->primes[c->n_q + k] % m, m);
     ka.P_mod[r] = centred(pm, m);
   }
-  int* d_rot = nullptr;
-  uint32_t* d_gal = nullptr;
-  if (nk > 0) {
-    HIP_TRY(hipMalloc((void**)&d_rot, sizeof(int) * nk));
-    HIP_TRY(hipMalloc((void**)&d_gal, sizeof(uint32_t) * nk));
-    HIP_TRY(hipMemcpy(d_rot, rk->rot.data(), sizeof(int) * nk, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d_gal, rk->galois.data(), sizeof(uint32_t) * nk, hipMemcpyHostToDevice));
-    // bounded chunks so a single launch stays modest
-    const int per = 64;
-    for (int k0 = 0; k0 < nk; k0 += per) {
-      const int cnt = std::min(per, nk - k0);
-      HIP_TRY(launch_rotkey_gen(launch_ctx(c, nullptr), sk->s, d_rot + k0, d_gal + k0, cnt, seed, ka,
-                                rk->keys + (size_t)k0 * rk->key_stride));
+  // bounded launches, the keys of each passed by value
+  for (int k0 = 0; k0 < nk; k0 += kKeysPerLaunch) {
+    const int cnt = std::min(kKeysPerLaunch, nk - k0);
+    RotKeyList list{};
+    for (int u = 0; u < cnt; ++u) {
+      list.rot[u] = rk->rot[k0 + u];
+      list.galois[u] = rk->galois[k0 + u];
     }
+    HIP_TRY(launch_rotkey_gen(launch_ctx(c, nullptr), sk->s, list, cnt, seed, ka,
+                              rk->keys + (size_t)k0 * rk->key_stride));
   }
   HIP_TRY(hipDeviceSynchronize());
-  if (d_rot) (void)hipFree(d_rot);
-  if (d_gal) (void)hipFree(d_gal);
   *out = rk.release();
   return PVFL_OK;
 }

@@ -94,9 +94,6 @@ struct pvfl_plan {
   int chunks_per_giant = 1;    // BSGS: chunks of one giant step's inner sum
   // DIAG plan: in-ciphertext RaS rotations; ROW plan: per-row data
   std::vector<int> ras_rots;
-  // private workspace when the caller passes none
-  mutable double* own_ws = nullptr;
-  mutable size_t own_ws_bytes = 0;
   ~pvfl_plan();
 };
 

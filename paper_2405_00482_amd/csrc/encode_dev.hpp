@@ -246,7 +246,7 @@ __device__ __forceinline__ void gather_kind(const EncodeArgs& a, int k, double s
   for (int u = 0; u < CNT; ++u) id[u] = CT ? ct_slot_index<KIND>(a, k, slot_of(u)) : pt_slot_index<KIND>(a, k, slot_of(u));
   double x[CNT];
 #pragma unroll
-  for (int u = 0; u < CNT; ++u) x[u] = a.X[id[u] < 0 ? 0 : id[u]];
+  for (int u = 0; u < CNT; ++u) x[u] = gmem(a.X)[id[u] < 0 ? 0 : id[u]];
 #pragma unroll
   for (int u = 0; u < CNT; ++u) v[u] = id[u] < 0 ? 0.0 : x[u] * scale;
 }

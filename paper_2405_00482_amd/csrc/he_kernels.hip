@@ -206,8 +206,7 @@ NTT_KERNEL(LOGN) void k_decrypt_f64(const double* __restrict__ ct, const double*
 // with phi_g(s) read as an orbit shift of the transformed secret.
 // Layout: keys[kk][j][0 = b | 1 = a][r][N].
 template <int LOGN>
-NTT_KERNEL(LOGN) void k_rotkey_gen(const double* __restrict__ sk, const int* __restrict__ rot_of_key,
-                                    const uint32_t* __restrict__ galois_of_key, uint64_t seed, RotKeyArgs ka,
+NTT_KERNEL(LOGN) void k_rotkey_gen(const double* __restrict__ sk, RotKeyList list, uint64_t seed, RotKeyArgs ka,
                                     double* __restrict__ keys, DevTabs tb) {
   constexpr int N = 1 << LOGN;
   NTT_LDS(LOGN);
@@ -216,8 +215,8 @@ NTT_KERNEL(LOGN) void k_rotkey_gen(const double* __restrict__ sk, const int* __r
   const int j = (blockIdx.x / nlimb) % ka.beta;
   const int kk = blockIdx.x / (nlimb * ka.beta);
   const ModQ m = tb.mods[r];  // limbs of Q_L u P are exactly the context's prime order
-  const uint64_t g = galois_of_key[kk];
-  const int rot = rot_of_key[kk];
+  const uint64_t g = list.galois[kk];
+  const int rot = list.rot[kk];
   const uint64_t sa = kStreamKeyA | ((uint64_t)j << 40) | ((uint64_t)r << 24) | g;
   const uint64_t se = kStreamKeyE | ((uint64_t)j << 40) | g;
   double* kb = keys + ((((size_t)kk * ka.beta + j) * 2 + 0) * nlimb + r) * N;
@@ -643,15 +642,16 @@ hipError_t launch_decrypt_f64(const LaunchCtx& L, const double* ct, int nct, con
 }
 
 template <int LOGN>
-static void rotkey_impl(const LaunchCtx& L, const double* sk, const int* rot_of_key, const uint32_t* gal, int nkeys,
-                        uint64_t seed, const RotKeyArgs& ka, double* keys) {
+static void rotkey_impl(const LaunchCtx& L, const double* sk, const RotKeyList& list, int nkeys, uint64_t seed,
+                        const RotKeyArgs& ka, double* keys) {
   hipLaunchKernelGGL(k_rotkey_gen<LOGN>, dim3(nkeys * ka.beta * ka.n_limbs), dim3(NttShape<LOGN>::T), 0, L.stream,
-                     sk, rot_of_key, gal, seed, ka, keys, L.tb);
+                     sk, list, seed, ka, keys, L.tb);
 }
-hipError_t launch_rotkey_gen(const LaunchCtx& L, const double* sk, const int* rot_of_key, const uint32_t* gal, int nkeys,
-                             uint64_t seed, const RotKeyArgs& ka, double* keys) {
+hipError_t launch_rotkey_gen(const LaunchCtx& L, const double* sk, const RotKeyList& list, int nkeys, uint64_t seed,
+                             const RotKeyArgs& ka, double* keys) {
   if (nkeys <= 0) return hipSuccess;
-  DISPATCH_LOGN(L, rotkey_impl, L, sk, rot_of_key, gal, nkeys, seed, ka, keys);
+  if (nkeys > kKeysPerLaunch) return hipErrorInvalidValue;
+  DISPATCH_LOGN(L, rotkey_impl, L, sk, list, nkeys, seed, ka, keys);
   return hipGetLastError();
 }
 

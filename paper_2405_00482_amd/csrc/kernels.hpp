@@ -59,6 +59,14 @@ struct RotKeyArgs {
   double P_mod[kMaxLimbs];
 };
 
+// Up to kKeysPerLaunch rotation keys of one generation launch, passed by
+// value: rotation amount and Galois element of each.
+constexpr int kKeysPerLaunch = 64;
+struct RotKeyList {
+  int rot[kKeysPerLaunch];
+  uint32_t galois[kKeysPerLaunch];
+};
+
 struct RescaleArgs {
   double half_mod_last;            // floor(q_l / 2)
   double half_mod[kMaxLimbs];      // floor(q_l / 2) mod q_i
@@ -94,8 +102,8 @@ hipError_t launch_encrypt(const LaunchCtx& L, const int64_t* msg, int nct, const
 hipError_t launch_decrypt_u64(const LaunchCtx& L, const double* ct, const double* sk, int lv, uint64_t* out);
 hipError_t launch_decrypt_f64(const LaunchCtx& L, const double* ct, int nct, const double* sk, int lv, double* out,
                               const double* const* ct_tab = nullptr);
-hipError_t launch_rotkey_gen(const LaunchCtx& L, const double* sk, const int* rot_of_key, const uint32_t* gal, int nkeys,
-                             uint64_t seed, const RotKeyArgs& ka, double* keys);
+hipError_t launch_rotkey_gen(const LaunchCtx& L, const double* sk, const RotKeyList& list, int nkeys, uint64_t seed,
+                             const RotKeyArgs& ka, double* keys);
 // ModUp of the c1 halves of nct ciphertexts (ct + c*ct_stride); y holds
 // [nct][lv+1][N] coefficient scratch; digits of ciphertext c at digits + c*dig_stride
 hipError_t launch_modup(const LaunchCtx& L, const double* ct, size_t ct_stride, int nct, int lv, const KsLevel* kl_dev,

@@ -57,6 +57,16 @@ struct NttShape {
 
 __device__ __forceinline__ int lds_pad(int j) { return j + (j >> 4); }
 
+// Global-memory views of device pointers.  A load through a generic pointer
+// is a flat load, which the hardware counts against the LDS wait counter as
+// well: waiting for a kernel's LDS reads would then also wait for every
+// global load in flight.  Global loads count against the vector-memory
+// counter only.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 // The thread index.  A source file that defines PVFL_OPAQUE_TID before
 // including this header gets it hidden from loop-invariant code motion (the
 // empty asm statement may change it as far as the compiler knows): its

@@ -47,7 +47,6 @@ static int ilog2(int x) {
 pvfl_plan::~pvfl_plan() {
   if (iota_dev) (void)hipFree(iota_dev);
   if (rot_dev) (void)hipFree(rot_dev);
-  if (own_ws) (void)hipFree(own_ws);
 }
 
 static uint32_t galois_rotl(int i, int N) {
@@ -311,21 +310,13 @@ extern "C" size_t pvfl_bytes_workspace_sum(const pvfl_plan* p, int32_t count) {
   return p && count >= 1 ? sizeof(double) * std::max<size_t>(ws_doubles(p, count), 1) : 0;
 }
 
+// the caller's workspace (plans with no workspace -- CTMAT, COL -- take NULL)
 static pvfl_status get_ws(const pvfl_plan* p, void* ws, size_t ws_bytes, double** out, int count = 1) {
+  *out = (double*)ws;
+  if (ws_doubles(p, count) == 0) return PVFL_OK;
   const size_t need = pvfl_bytes_workspace_sum(p, count);
-  if (ws) {
-    if (ws_bytes < need) return fail(PVFL_E_SHAPE, "workspace too small");
-    *out = (double*)ws;
-    return PVFL_OK;
-  }
-  if (p->own_ws_bytes < need) {
-    if (p->own_ws) (void)hipFree(p->own_ws);
-    p->own_ws = nullptr;
-    p->own_ws_bytes = 0;
-    if (hipMalloc((void**)&p->own_ws, need) != hipSuccess) return fail(PVFL_E_NOMEM, "workspace allocation");
-    p->own_ws_bytes = need;
-  }
-  *out = p->own_ws;
+  if (!ws) return fail(PVFL_E_INVALID, "the plan needs a workspace of " + std::to_string(need) + " bytes");
+  if (ws_bytes < need) return fail(PVFL_E_SHAPE, "workspace too small");
   return PVFL_OK;
 }
 

@@ -86,7 +86,7 @@ def lib():
         sig = {
             "pvfl_context_create": [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(_VP)],
             "pvfl_keygen": [_VP, u64, ctypes.POINTER(_VP)],
-            "pvfl_rotkeys_gen": [_VP, _VP, ctypes.POINTER(u32), i32, u64, ctypes.POINTER(_VP)],
+            "pvfl_rotkeys_gen": [_VP, _VP, ctypes.POINTER(u32), i32, u64, _VP, sz, ctypes.POINTER(_VP)],
             "pvfl_plan_create": [_VP, ctypes.POINTER(PlanOpts), ctypes.POINTER(_VP)],
             "pvfl_plan_get_info": [_VP, ctypes.POINTER(PlanInfo)],
             "pvfl_plan_galois": [_VP, ctypes.POINTER(u32), i32],
@@ -132,7 +132,9 @@ def lib():
             "pvfl_mlp_train_step": [_VP, _VP, _VP, i32, ctypes.c_float, _VP, _VP],
             "pvfl_batch_create": [_VP, i32, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
-                                  ctypes.POINTER(_VP), _VP, ctypes.POINTER(BatchOpts), ctypes.POINTER(_VP)],
+                                  ctypes.POINTER(_VP), _VP, ctypes.POINTER(BatchOpts), _VP, sz, ctypes.POINTER(_VP)],
+            "pvfl_batch_workspace_bytes": [_VP, i32, ctypes.POINTER(_VP), ctypes.POINTER(BatchOpts),
+                                           ctypes.POINTER(sz)],
             "pvfl_batch_encode": [_VP, _VP],
             "pvfl_batch_encrypt": [_VP, _VP, u64, _VP],
             "pvfl_batch_matmul": [_VP, _VP],
@@ -154,6 +156,8 @@ def lib():
             f.restype = sz
         L.pvfl_noalloc_max_bytes.argtypes = []
         L.pvfl_noalloc_max_bytes.restype = sz
+        L.pvfl_bytes_rotkeys.argtypes = [_VP, i32]
+        L.pvfl_bytes_rotkeys.restype = sz
         L.pvfl_bytes_workspace_sum.argtypes = [_VP, i32]
         L.pvfl_bytes_workspace_sum.restype = sz
         L.pvfl_mlp_num_params.argtypes = [_VP]
@@ -241,6 +245,7 @@ class Context(_Handle):
 
     def __init__(self, logN: int, q, p, log2_scale: float, device: int = 0):
         self.logN, self.N = logN, 1 << logN
+        self.device = device
         self.q, self.p = [int(x) for x in q], [int(x) for x in p]
         self.log2_scale = log2_scale
         qa = (ctypes.c_uint64 * len(self.q))(*self.q)
@@ -273,11 +278,17 @@ class Context(_Handle):
         return PublicKey(h, keep=(self,))
 
     def rotkeys(self, sk: "SecretKey", galois, seed: int) -> "RotKeys":
+        """rotation keys for the Galois elements, in a torch device buffer this
+        handle keeps alive"""
+        import torch
         g = [int(x) for x in galois]
         arr = (ctypes.c_uint32 * max(1, len(g)))(*g)
+        nb = int(lib().pvfl_bytes_rotkeys(self.h, len(set(g))))
+        buf = torch.empty(nb, dtype=torch.uint8, device=f"cuda:{self.device}")
         h = _VP()
-        _check(lib().pvfl_rotkeys_gen(self.h, sk.h, arr, len(g), seed, ctypes.byref(h)))
-        return RotKeys(h, list(g), keep=(self,))
+        _check(lib().pvfl_rotkeys_gen(self.h, sk.h, arr, len(g), seed, ctypes.c_void_p(buf.data_ptr()), nb,
+                                      ctypes.byref(h)))
+        return RotKeys(h, list(dict.fromkeys(g)), keep=(self, buf))
 
     def candidates(self, m: int, n: int, level: int = -1, operand: int = 0, n_out: int = 0) -> list:
         """every valid candidate: option dict plus "batch" (products it runs)"""
@@ -452,7 +463,9 @@ class Plan(_Handle):
         ca = (_VP * n)(*[_dev(t, f"ciphertexts {k}", self.bytes("ct_in")).value for k, t in enumerate(cts)])
         pa = (_VP * n)(*[_dev(t, f"plaintexts {k}", self.bytes("pt")).value for k, t in enumerate(pts)])
         o = _dev(out, "output", self.bytes("ct_out"))
-        w = _dev(ws, "workspace", self.workspace_sum_bytes(n)) if ws is not None else _ptr(None)
+        if ws is None:
+            ws = self.workspace(n)
+        w = _dev(ws, "workspace", self.workspace_sum_bytes(n), str(ws.dtype)[6:]) if ws is not None else _ptr(None)
         ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
         _check(lib().pvfl_matmul_ct_pt_sum(self.h, n, ca, pa, keys.h if keys is not None else None, o, w, ws_bytes,
                                            _stream()))
@@ -517,11 +530,24 @@ class Plan(_Handle):
         _check(lib().pvfl_plan_analytic_ms(self.h, batch, c, ctypes.byref(out)))
         return out.value
 
+    def workspace(self, count: int = 1):
+        """a device workspace for this plan's products (count terms), kept with
+        the plan and reused; None for plans that need none"""
+        import torch
+        nb = self.bytes("workspace") if count == 1 else self.workspace_sum_bytes(count)
+        if self.info["kind"] in (PLAN_CTMAT, PLAN_COL):
+            return None
+        if getattr(self, "_ws", None) is None or self._ws.numel() < nb:
+            self._ws = torch.empty(nb, dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+        return self._ws
+
     def matmul(self, ct, pt, keys, out, ws=None):
         c = _dev(ct, "ciphertexts", self.bytes("ct_in"))
         p = _dev(pt, "plaintexts", self.bytes("pt"))
         o = _dev(out, "output", self.bytes("ct_out"))
-        w = _dev(ws, "workspace", self.bytes("workspace")) if ws is not None else _ptr(None)
+        if ws is None:
+            ws = self.workspace()
+        w = _dev(ws, "workspace", self.bytes("workspace"), str(ws.dtype)[6:]) if ws is not None else _ptr(None)
         ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
         _check(lib().pvfl_matmul_ct_pt(self.h, c, p, keys.h if keys is not None else None, o, w, ws_bytes, _stream()))
 
@@ -592,9 +618,16 @@ class Batch(_Handle):
     _destroy = "pvfl_batch_destroy"
 
     def __init__(self, ctx: Context, plans, X=None, v=None, pt=None, ct=None, out=None, y=None, keys=None,
-                 group: int = 2, chunk: int = 32, vec: int = 1, chunk_major: bool = True):
+                 group: int = 2, chunk: int = 32, vec: int = 1, chunk_major: bool = True, ws=None):
+        import torch
         n = len(plans)
         plan_arr = (_VP * n)(*[p.h.value for p in plans])
+        opts = BatchOpts(group, chunk, vec, int(chunk_major))
+        need = ctypes.c_size_t()
+        _check(lib().pvfl_batch_workspace_bytes(ctx.h, n, plan_arr, ctypes.byref(opts), ctypes.byref(need)))
+        if ws is None:
+            ws = torch.empty(need.value, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        wsp = _dev(ws, "workspace", need.value, str(ws.dtype)[6:])
         for name, lst in (("pt", pt), ("ct", ct), ("out", out), ("X", X), ("v", v), ("y", y)):
             if lst is not None and len(lst) != n:
                 raise PvflError(E_INVALID, f"{name}: one entry per product")
@@ -616,8 +649,9 @@ class Batch(_Handle):
                                        _ptr_array(pt), _ptr_array(ct), _ptr_array(out),
                                        _ptr_array(y) if y is not None else None,
                                        keys.h if keys is not None else None,
-                                       ctypes.byref(BatchOpts(group, chunk, vec, int(chunk_major))), ctypes.byref(h)))
-        super().__init__(h, keep=(ctx, plans, X, v, pt, ct, out, y, keys))
+                                       ctypes.byref(opts), wsp, ws.numel() * ws.element_size(), ctypes.byref(h)))
+        super().__init__(h, keep=(ctx, plans, X, v, pt, ct, out, y, keys, ws))
+        self.workspace_bytes = need.value
 
     def encode(self):
         _check(lib().pvfl_batch_encode(self.h, _stream()))

@@ -50,10 +50,14 @@ def _same(a, b, what):
 @pytest.mark.parametrize("name,shapes,group,chunk,vec", [
     ("C1", [(16, 256), (100, 37), (64, 64), (8, 2048)], 2, 4, 1),
     ("C1", [(16, 256), (100, 37), (64, 64), (8, 2048)], 4, 64, 2),
+    ("C1", [(16, 256), (100, 37), (64, 64), (8, 2048)], 2, 5, 2),     # odd chunk
     ("C3", W.c3_shapes(64)[:6], 4, 16, 2),
     ("C3", W.c3_shapes(64)[:6], 1, 1024, 1),
+    ("C3", W.c3_shapes(64)[:6], 4, 7, 1),
     ("C4", [(16, 256), (3, 5), (300, 700)], 2, 32, 2),     # three special primes, two digits
+    ("C4", [(16, 256), (3, 5), (300, 700)], 2, 9, 2),
     ("C5", [(16, 4096), (3, 5), (40, 1000)], 2, 32, 1),    # ring 2^15, split transforms
+    ("C5", [(16, 4096), (3, 5), (40, 1000)], 2, 3, 2),
 ])
 def test_batch_equals_percall(name, shapes, group, chunk, vec):
     ctx, sk, plans, keys, X, v, bufs = _setup(name, shapes)
@@ -111,3 +115,29 @@ def test_batch_rejects_bad_plans():
     with pytest.raises(pvfl.PvflError) as e:   # rotations needed, no keys given
         pvfl.Batch(ctx, [p], pt=[bufs[0]], ct=[bufs[1]], out=[bufs[2]])
     assert e.value.status == -4
+
+
+def test_batch_without_rotations_needs_no_keys():
+    """every product with m' = 1 (no rotation): the batch runs with no key set
+    and equals the per-call form"""
+    shapes = [(3, 5), (16, 64), (1, 1)]
+    t = torch()
+    ctx = context("C1")
+    sk = ctx.keygen(3)
+    plans = [ctx.plan(pvfl.PLAN_HYBRID, m, n, lazy=True) for (m, n) in shapes]
+    assert all(p.info["mprime"] == 1 and not p.galois() for p in plans)
+    rng = np.random.default_rng(9)
+    f = dict(dtype=t.float64, device="cuda")
+    X = [t.from_numpy(rng.standard_normal((m, n))).cuda() for (m, n) in shapes]
+    v = [t.from_numpy(rng.uniform(-1, 1, n)).cuda() for (m, n) in shapes]
+
+    def bufs():
+        return ([t.zeros(p.bytes("pt") // 8, **f) for p in plans], [t.zeros(p.bytes("ct_in") // 8, **f) for p in plans],
+                [t.zeros(p.bytes("ct_out") // 8, **f) for p in plans], [t.zeros(m, **f) for (m, n) in shapes])
+    ref = _percall(plans, sk, None, X, v, bufs, 40)
+    pt, ct, out, y = bufs()
+    b = pvfl.Batch(ctx, plans, X=X, v=v, pt=pt, ct=ct, out=out, y=y, keys=None, group=2, chunk=8, vec=2)
+    b.run(sk, 40, graph=False)
+    t.cuda.synchronize()
+    _same(out, ref[2], "products")
+    _same(y, ref[3], "decoded results")

@@ -134,10 +134,12 @@ def setup(name):
 @pytest.mark.parametrize("name,shapes,group,chunk,vec", [
     # m' = 64 in 8 chunks (the partial-sum kernel's eight-loads loop) beside m' = 16
     ("C3", [(256, 2048), (64, 2048)], 2, 8, 2),
-    # three special primes, two digits: m' = 64 in 16 chunks, m' = 8, m' = 1
+    # three special primes, two digits: m' = 64 in 16 and 22 chunks, m' = 8, m' = 1
     ("C4", [(300, 700), (40, 1000), (16, 256)], 2, 4, 2),
+    ("C4", [(300, 700), (40, 1000), (16, 256)], 4, 3, 1),
     # ring 2^15 (split transforms): m' = 16 in 8 chunks beside a one-diagonal product
     ("C5", [(64, 4096), (3, 5)], 2, 2, 1),
+    ("C5", [(64, 4096), (3, 5)], 2, 2, 2),
 ])
 def test_batch_many_chunks_bit_exact(name, shapes, group, chunk, vec):
     prm, ctx, sk, s = setup(name)
@@ -148,7 +150,7 @@ def test_batch_many_chunks_bit_exact(name, shapes, group, chunk, vec):
         X = rng.standard_normal((m, n))
         y = rng.uniform(-1, 1, n)
         prods.append(Product(prm, ctx, sk, s, p, X, y, SEED_ENC + 100 * k))
-    assert max(p.oplan.mprime // chunk for p in prods) >= 8
+    assert max(-(-p.oplan.mprime // chunk) for p in prods) >= 8
     gal = sorted(set(g for p in plans for g in p.galois()))
     keys = ctx.rotkeys(sk, gal, SEED_KEYS)
     b = pvfl.Batch(ctx, plans, pt=[p.pt for p in prods], ct=[p.ct for p in prods], out=[p.out for p in prods],
