@@ -44,7 +44,7 @@ FEATURE_NAMES = ("log2_N", "limbs", "alpha", "beta", "K", "log2_m", "log2_n", "l
                  "lg_rot", "lg_hstrot", "lg_modup", "lg_moddown", "lg_pt_limbs", "lg_keys", "lg_blocks")
 assert len(FEATURE_NAMES) == pvfl.PLAN_FEATURES
 
-VEC_CONFIGS = ["C1", "C2", "C3", "C4", "C4a1", "C4a2"]
+VEC_CONFIGS = ["C1", "C2", "C3", "C4", "C4a1", "C4a2", "C5"]
 MAT_CONFIGS = ["C4", "C4a1", "C4a2"]
 
 
@@ -326,7 +326,7 @@ def paper_default(r) -> bool:
     """the paper's choices: the hybrid with hoisted rotations for X [[y]]
     (Sec. 4) and Alg. 3 for [[A]] W (Sec. 5), on the configured digit count"""
     o = r["opts"]
-    if r["config"] not in ("C1", "C2", "C3", "C4"):
+    if r["config"] not in ("C1", "C2", "C3", "C4", "C5"):
         return False
     if r.get("operand", 0) == 1:
         return o["kind"] == 3 and o.get("pack", 1) == 1

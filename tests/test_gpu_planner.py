@@ -68,6 +68,11 @@ def test_learned_planner_regret_within_ten_percent(trained):
         assert mlp["mean"] < dflt["mean"], label
     # and, over all shapes, against the operation-count model it replaces
     assert res["mlp"]["mean"] <= res["analytic"]["mean"]
+    # the ring 2^15 shapes (8 + 2 primes, four digits) on their own
+    c5 = [o["regret"] for o in res["X[[y]]"]["mlp"]["shapes"] if o["config"] == "C5"]
+    assert c5, "no held-out C5 shapes"
+    print(f"C5: network regret mean {np.mean(c5):.4f} max {np.max(c5):.4f} over {len(c5)} held-out shapes")
+    assert np.mean(c5) <= 0.10
 
 
 def test_native_choice_agrees_with_network(db, trained):
@@ -75,7 +80,7 @@ def test_native_choice_agrees_with_network(db, trained):
     _, test = P.split(db)
     planner = pvfl.Planner(net, st.x_mean, st.x_std, st.y_mean, st.y_std)
     seen = 0
-    for cfg, operand in (("C1", 0), ("C2", 0), ("C4", 1)):
+    for cfg, operand in (("C1", 0), ("C2", 0), ("C4", 1), ("C5", 0)):
         ctx = context(cfg)
         sel = [r for r in test if r["config"] == cfg and r.get("operand", 0) == operand]
         shapes = sorted(set((r["idx"], r["m"], r["n"], r.get("n_out", 0)) for r in sel))[:6]
