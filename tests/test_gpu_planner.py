@@ -110,3 +110,77 @@ def test_native_analytic_choice_agrees(db, trained):
         assert abs(ms - float(np.min(pred))) <= 1e-9 * max(1.0, ms)
         best = [r["opts"] for r, p in zip(rows, pred) if abs(p - np.min(pred)) <= 1e-12 * max(1.0, p)]
         assert any({k: got[k] for k in o} == o for o in best)
+
+
+def test_batch_against_planner_picks_per_call(trained):
+    """The batched form fuses only the lazy hybrid (every product accumulates
+    its rotations in Q u P, so one key tile serves every product that has
+    that diagonal).  For the 64-product 2^14 workload the learned planner
+    picks the lazy hybrid for every product (some with baby-step giant-step,
+    which the batch does not use); running each product alone with its pick
+    must still be slower than the batched step, and every pick must decrypt
+    to X r."""
+    import time
+    _, net, st = trained
+    t = torch()
+    planner = pvfl.Planner(net, st.x_mean, st.x_std, st.y_mean, st.y_std)
+    ctx = context("C3")
+    sd = W.seeds("C3")
+    shapes = W.c3_shapes(64)
+    chosen = [planner.choose(ctx, m, n)[0] for (m, n) in shapes]
+    picks = [ctx.plan_from(o) for o in chosen]
+    lazy = [ctx.plan(pvfl.PLAN_HYBRID, m, n, lazy=True) for (m, n) in shapes]
+    kinds = {}
+    for o in chosen:
+        key = (o["kind"], o["lazy_moddown"], o["bsgs"] > 0)
+        kinds[key] = kinds.get(key, 0) + 1
+    assert all(o["kind"] == pvfl.PLAN_HYBRID and o["lazy_moddown"] == 1 for o in chosen), kinds
+    gal = sorted(set(g for p in picks + lazy for g in p.galois()))
+    sk = ctx.keygen(sd["sk"])
+    keys = ctx.rotkeys(sk, gal, sd["rotkeys"])
+    f64 = dict(dtype=t.float64, device="cuda")
+    Xs, rs = [], []
+    for k, (m, n) in enumerate(shapes):
+        XT, r = W.c3_inputs(k, (m, n))
+        Xs.append(t.from_numpy(XT).to("cuda"))
+        rs.append(t.from_numpy(r).to("cuda"))
+
+    def buffers(plans):
+        return ([t.empty(p.bytes("pt") // 8, **f64) for p in plans], [t.empty(p.bytes("ct_in") // 8, **f64) for p in plans],
+                [t.empty(p.bytes("ct_out") // 8, **f64) for p in plans], [t.empty(m, **f64) for (m, _) in shapes])
+
+    def check(ys):
+        for k in range(len(shapes)):
+            want = Xs[k].cpu().numpy() @ rs[k].cpu().numpy()
+            got = ys[k].cpu().numpy()
+            assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2.0 ** -20, k
+
+    def timed(fn, reps=3):
+        fn()
+        t.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        t.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    pts, cts, outs, ys = buffers(picks)
+    ws = t.empty(max(p.bytes("workspace") for p in picks) // 8 + 1, **f64)
+
+    def percall():
+        for k, p in enumerate(picks):
+            p.encode_pt(Xs[k], pts[k])
+            p.encrypt(sk, rs[k], sd["enc"] + k, cts[k])
+            p.matmul(cts[k], pts[k], keys, outs[k], ws)
+            p.decrypt_decode(sk, outs[k], ys[k])
+
+    ms_picks = timed(percall)
+    check(ys)
+    bpts, bcts, bouts, bys = buffers(lazy)
+    batch = pvfl.Batch(ctx, lazy, X=Xs, v=rs, pt=bpts, ct=bcts, out=bouts, y=bys, keys=keys,
+                       group=2, chunk=64, vec=2)
+    ms_batch = timed(lambda: batch.run(sk, sd["enc"], graph=True))
+    check(bys)
+    print(f"planner picks (kind, lazy, bsgs): count {kinds}; per call with the picks {ms_picks:.2f} ms, "
+          f"batched lazy hybrid {ms_batch:.2f} ms")
+    assert ms_batch < ms_picks
