@@ -161,9 +161,11 @@ __global__ __launch_bounds__(256) void k_diag_batch(BatchDiagArgs a) {
       for (int v = 0; v < V; ++v) {
         // spos(tl + sh + v), written out with tl = 2 tid for V = 2
         const int pos = V == 2 ? ((sh + v) & 1) * hw + (int)threadIdx.x + ((sh + v) >> 1) : tl + sh + v;
-        double u0 = 0.0, u1 = 0.0;
+        // the sums start from their first term (adding it to 0.0 would cost an instruction)
+        const double d0 = st[pos];
+        double u0 = mulmod(d0, kb[0][v], m), u1 = mulmod(d0, ka[0][v], m);
 #pragma unroll
-        for (int j = 0; j < BETA; ++j) {
+        for (int j = 1; j < BETA; ++j) {
           const double d = st[(size_t)j * win + pos];
           u0 += mulmod(d, kb[j][v], m);
           u1 += mulmod(d, ka[j][v], m);
