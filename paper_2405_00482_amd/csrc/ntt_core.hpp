@@ -189,8 +189,13 @@ __device__ __forceinline__ void ntt_fwd_regs(double* s, const double (&c)[16], c
   static_assert(LOGN >= 12 && LOGN <= 14, "one wave owns 1024 elements of an LDS-resident limb");
   double x[16];
   const int tid = opaque_tid();
+  // the first stage adds x[u] (u < 8) to a twiddle product of x[u + 8]:
+  // mulmod takes |x[u + 8]| < 2^51 as it is, so only the addends are
+  // re-centred, and every value after the stage obeys the same bound
 #pragma unroll
-  for (int u = 0; u < 16; ++u) x[u] = reduce(c[u], m);
+  for (int u = 0; u < 8; ++u) x[u] = reduce(c[u], m);
+#pragma unroll
+  for (int u = 8; u < 16; ++u) x[u] = c[u];
   {
     const int base[1] = {tid};
     ct_pass_regs<LOGN, 4>(x, 0, base, tw, m);
