@@ -61,6 +61,33 @@ NTT_KERNEL(LOGN) void k_import_i64(const int64_t* __restrict__ in, double* __res
                     [&](int t, double v) { dst[t] = v; });
 }
 
+// The same at N <= 2^14 with one workgroup per polynomial: the integer row is
+// read once, into registers, and every limb is reduced from it and
+// transformed in turn, so the row's memory latency is paid once per
+// polynomial instead of once per limb.
+template <int LOGN>
+NTT_KERNEL(LOGN) void k_import_i64_poly(const int64_t* __restrict__ in, double* __restrict__ out, LimbMap map,
+                                        DevTabs tb) {
+  static_assert(LOGN <= 14, "one LDS-resident limb");
+  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
+  NTT_LDS(LOGN);
+  const int c = blockIdx.x;
+  const int64_t* src = in + (size_t)c * N;
+  int64_t v[16];
+#pragma unroll
+  for (int w = 0; w < 16; ++w) v[w] = src[opaque_tid() + w * T];
+  for (int l = 0; l < map.n; ++l) {
+    const int pi = map.idx[l];
+    const ModQ m = tb.mods[pi];
+    const double t32 = tb.two32[pi];
+    double x[16];
+#pragma unroll
+    for (int w = 0; w < 16; ++w) x[w] = i64_to_res(v[w], m, t32);
+    double* dst = out + ((size_t)c * map.n + l) * N;
+    ntt_fwd_regs_out<LOGN>(s, x, tb.fwd_tw + (size_t)pi * N, tb.perm, m, [&](int t, double y) { dst[t] = y; });
+  }
+}
+
 // evaluation-domain residues -> canonical coefficient residues as uint64
 template <int LOGN>
 NTT_KERNEL(LOGN) void k_export_u64(const double* __restrict__ in, uint64_t* __restrict__ out, LimbMap map, DevTabs tb) {
@@ -72,6 +99,55 @@ NTT_KERNEL(LOGN) void k_export_u64(const double* __restrict__ in, uint64_t* __re
   uint64_t* dst = out + (size_t)b * N;
   ntt_inv_in<LOGN>(s, [&](int t) { return src[t]; }, tb.inv_tw + (size_t)pi * N, tb.perm, m, tb.ninv[pi],
                    [&](int j, double v) { dst[j] = f64_to_u64(canon(v, m)); });
+}
+
+// The same at N <= 2^14 with one workgroup per polynomial: while one limb is
+// transformed, the next limb's values are already being loaded into
+// registers (its slots go to LDS only after this limb's transform is done).
+template <int LOGN>
+NTT_KERNEL(LOGN) void k_export_u64_poly(const double* __restrict__ in, uint64_t* __restrict__ out, LimbMap map,
+                                        DevTabs tb) {
+  static_assert(LOGN <= 14, "one LDS-resident limb");
+  constexpr int N = 1 << LOGN, T = NttShape<LOGN>::T;
+  NTT_LDS(LOGN);
+  const int c = blockIdx.x;
+  const double* src = in + (size_t)c * map.n * N;
+  // v[2w], v[2w+1]: orbit slots t = tid + w T and t + N/2 of the current limb
+  double v[16];
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    v[2 * w] = src[opaque_tid() + w * T];
+    v[2 * w + 1] = src[opaque_tid() + w * T + N / 2];
+  }
+  for (int l = 0; l < map.n; ++l) {
+    const int pi = map.idx[l];
+    const ModQ m = tb.mods[pi];
+    {
+      OrbitWalk ow = OrbitWalk::start<LOGN>();
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        const int j = ow.brv_index<LOGN>();
+        s[lds_pad(j)] = reduce(v[2 * w], m);
+        s[lds_pad(j ^ (N - 1))] = reduce(v[2 * w + 1], m);
+        ow.next<LOGN>();
+      }
+    }
+    if (l + 1 < map.n) {
+      const double* nsrc = src + (size_t)(l + 1) * N;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        v[2 * w] = nsrc[opaque_tid() + w * T];
+        v[2 * w + 1] = nsrc[opaque_tid() + w * T + N / 2];
+      }
+    }
+    __syncthreads();
+    double cf[16];
+    ntt_inv_regs<LOGN>(s, cf, tb.inv_tw + (size_t)pi * N, m, tb.ninv[pi]);
+    uint64_t* dst = out + ((size_t)c * map.n + l) * N;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) dst[opaque_tid() + w * T] = f64_to_u64(canon(cf[w], m));
+    __syncthreads();  // other threads may still read this limb from LDS
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -557,8 +633,20 @@ static void launch_ntt_all(const LaunchCtx& L, NttOp op, const void* in, void* o
   switch (op) {
     case NttOp::Fwd: hipLaunchKernelGGL(k_ntt_fwd<LOGN>, grid, block, 0, L.stream, (const double*)in, (double*)out, map, L.tb); break;
     case NttOp::Inv: hipLaunchKernelGGL(k_ntt_inv<LOGN>, grid, block, 0, L.stream, (const double*)in, (double*)out, map, L.tb); break;
-    case NttOp::ImportI64: hipLaunchKernelGGL(k_import_i64<LOGN>, grid, block, 0, L.stream, (const int64_t*)in, (double*)out, map, L.tb); break;
-    case NttOp::ExportU64: hipLaunchKernelGGL(k_export_u64<LOGN>, grid, block, 0, L.stream, (const double*)in, (uint64_t*)out, map, L.tb); break;
+    case NttOp::ImportI64:
+      if constexpr (LOGN <= 14)  // one workgroup per polynomial (nblocks = polynomials x limbs)
+        hipLaunchKernelGGL(k_import_i64_poly<LOGN>, dim3(nblocks / map.n), block, 0, L.stream, (const int64_t*)in,
+                           (double*)out, map, L.tb);
+      else
+        hipLaunchKernelGGL(k_import_i64<LOGN>, grid, block, 0, L.stream, (const int64_t*)in, (double*)out, map, L.tb);
+      break;
+    case NttOp::ExportU64:
+      if constexpr (LOGN <= 14)  // one workgroup per polynomial (nblocks = polynomials x limbs)
+        hipLaunchKernelGGL(k_export_u64_poly<LOGN>, dim3(nblocks / map.n), block, 0, L.stream, (const double*)in,
+                           (uint64_t*)out, map, L.tb);
+      else
+        hipLaunchKernelGGL(k_export_u64<LOGN>, grid, block, 0, L.stream, (const double*)in, (uint64_t*)out, map, L.tb);
+      break;
   }
 }
 
