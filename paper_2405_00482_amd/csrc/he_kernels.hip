@@ -73,18 +73,25 @@ NTT_KERNEL(LOGN) void k_import_i64_poly(const int64_t* __restrict__ in, double* 
   NTT_LDS(LOGN);
   const int c = blockIdx.x;
   const int64_t* src = in + (size_t)c * N;
-  int64_t v[16];
+  // v = hi 2^32 + lo, both parts exact in binary64, split once for all limbs
+  double hi[16], lo[16];
 #pragma unroll
-  for (int w = 0; w < 16; ++w) v[w] = src[opaque_tid() + w * T];
+  for (int w = 0; w < 16; ++w) {
+    const int64_t v = src[opaque_tid() + w * T];
+    hi[w] = (double)(v >> 32);
+    lo[w] = (double)(uint32_t)(v & 0xffffffffll);
+  }
   for (int l = 0; l < map.n; ++l) {
     const int pi = map.idx[l];
     const ModQ m = tb.mods[pi];
     const double t32 = tb.two32[pi];
     double x[16];
 #pragma unroll
-    for (int w = 0; w < 16; ++w) x[w] = i64_to_res(v[w], m, t32);
+    for (int w = 0; w < 16; ++w) x[w] = reduce(mulmod(reduce(hi[w], m), t32, m) + lo[w], m);  // as i64_to_res
     double* dst = out + ((size_t)c * map.n + l) * N;
-    ntt_fwd_regs_out<LOGN>(s, x, tb.fwd_tw + (size_t)pi * N, tb.perm, m, [&](int t, double y) { dst[t] = y; });
+    // nothing in this kernel reads the output again: stream it past L2
+    ntt_fwd_regs_out<LOGN>(s, x, tb.fwd_tw + (size_t)pi * N, tb.perm, m,
+                           [&](int t, double y) { __builtin_nontemporal_store(y, dst + t); });
   }
 }
 
@@ -145,7 +152,7 @@ NTT_KERNEL(LOGN) void k_export_u64_poly(const double* __restrict__ in, uint64_t*
     ntt_inv_regs<LOGN>(s, cf, tb.inv_tw + (size_t)pi * N, m, tb.ninv[pi]);
     uint64_t* dst = out + ((size_t)c * map.n + l) * N;
 #pragma unroll
-    for (int w = 0; w < 16; ++w) dst[opaque_tid() + w * T] = f64_to_u64(canon(cf[w], m));
+    for (int w = 0; w < 16; ++w) __builtin_nontemporal_store(f64_to_u64(canon(cf[w], m)), dst + opaque_tid() + w * T);
     __syncthreads();  // other threads may still read this limb from LDS
   }
 }
