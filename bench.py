@@ -40,30 +40,46 @@ def _cpu_sample(name, k, shape, n_diag, seeds):
     generation is set-up, done before the timer starts.  Returns the
     cleartext MACs covered (m n D / m') and the timed region's wall-clock
     start and end."""
+    from paper_2405_00482_amd import workloads as W
+    XT, r = W.c3_inputs(k, shape)
+    return _cpu_hybrid(name, XT, r, 0, n_diag, seeds, seeds["enc"] + k)
+
+
+def _cpu_c3_range(k, shape, d0, d1, seeds):
+    """product k of the C3 batch, diagonals [d0, d1)"""
+    from paper_2405_00482_amd import workloads as W
+    XT, r = W.c3_inputs(k, shape)
+    return _cpu_hybrid("C3", XT, r, d0, d1, seeds, seeds["enc"] + k)
+
+
+def _cpu_hybrid(name, XT, r, d0, d1, seeds, enc_seed):
+    """X^T [[r]] by the hybrid plan with lazy ModDown on the oracle, the terms
+    of diagonals [d0, d1) (d1 capped at m'; all of them for [0, m')); see
+    _cpu_sample.  The MACs credited are m n (d1 - d0) / m'."""
     from oracle import oracle as O
     from oracle import plans as PL
     from paper_2405_00482_amd import workloads as W
     prm = O.Params.from_dict(W.params_dict(name))
-    m, n = shape
-    XT, r = W.c3_inputs(k, shape)
+    m, n = XT.shape
     plan = PL.HybridPlan(m, n, prm.slots)
-    D = min(n_diag, plan.mprime)
+    d1 = min(d1, plan.mprime)
 
     class Trunc:
         def terms(self):
-            return [t for t in plan.terms() if t[1] < D]
+            return [t for t in plan.terms() if d0 <= t[1] < d1]
 
     s = O.keygen(prm, seeds["sk"])
     keys = {O.galois_rotl(i, prm.N): O.rotkey_gen(prm, s, O.galois_rotl(i, prm.N), seeds["rotkeys"])
-            for i in range(1, D)}
+            for i in range(max(d0, 1), d1)}
     t0 = time.time()
-    pts = [O.encode(PL.hybrid_pt_slots(plan, XT, 0, 0, i), prm.N, prm.scale) for i in range(D)]
-    ct = O.encrypt(prm, s, PL.hybrid_ct_ints(prm, plan, r, prm.scale)[0], prm.L, seeds["enc"] + k)
+    pts = [O.encode(PL.hybrid_pt_slots(plan, XT, 0, 0, i), prm.N, prm.scale) if d0 <= i < d1 else None
+           for i in range(d1)]
+    ct = O.encrypt(prm, s, PL.hybrid_ct_ints(prm, plan, r, prm.scale)[0], prm.L, enc_seed)
     out = PL.hybrid_matmul(prm, Trunc(), [ct], pts, keys, True)[0]
     z = O.decrypt_decode(prm, s, out, prm.scale ** 2)
     PL.hybrid_lazy_ras(plan, [z])
     t1 = time.time()
-    return m * n * D / plan.mprime, t0, t1
+    return m * n * (d1 - d0) / plan.mprime, t0, t1
 
 
 def _cpu_worker_ready(_):
@@ -131,6 +147,89 @@ def cpu_baseline(name, shapes, seeds, single_tasks=2, single_diag=16, pool_tasks
                                         f"{macs1:.3g} MACs in {dt1:.1f} s"},
             "macs_covered": macs_all, "fraction_of_step_macs": macs_all / step_macs,
             "cpu_model": model, "nproc": nproc, "usable_cpus": usable, "threads": workers}
+
+
+def _cpu_ctmat(A, B, seeds):
+    """[[A]] B by Alg. 3 on the oracle at C4 with the widest column packing,
+    the evaluating party's work as ctmat_c4 times it: encode B's plaintexts
+    and the product (A's diagonal ciphertexts are encrypted beforehand)."""
+    from oracle import oracle as O
+    from oracle import plans as PL
+    from paper_2405_00482_amd import workloads as W
+    prm = O.Params.from_dict(W.params_dict("C4"))
+    m, n = A.shape
+    nout = B.shape[1]
+    pack = prm.slots // max(m, n)
+    plan = PL.CtMatPlan(m, n, nout, prm.slots, pack)
+    s = O.keygen(prm, seeds["sk"])
+    cts = [O.encrypt(prm, s, O.encode(PL.ctmat_ct_slots(plan, A, i), prm.N, prm.scale), prm.L, seeds["enc"] + i)
+           for i in range(plan.ndiag)]
+    t0 = time.time()
+    pts = [O.encode(PL.ctmat_pt_slots(plan, B, i, k), prm.N, prm.scale)
+           for i in range(plan.ndiag) for k in range(plan.n_out_cts)]
+    PL.ctmat_matmul(prm, plan, cts, pts)
+    return m * n * nout, time.time() - t0, pack
+
+
+def cpu_full(max_workers=16) -> dict:
+    """The CPU oracle on whole configurations (not part of the default run):
+    C1 and C2 (one X^T [[r]] product each, every diagonal) and C4 (Alg. 3
+    forward and backward) on one thread; C3's 64 products, every diagonal,
+    over a process pool (one product per task, largest first; the rate is
+    all MACs over the span from the first task's start to the last one's
+    end); C5 (N = 2^15) truncated to one column and its first 64 diagonals,
+    labelled as such.  Rotation keys are generated before each timer starts."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_2405_00482_amd import workloads as W
+    from oracle import plans as PL
+    model, nproc, usable = _host_cpu()
+    res = {"cpu_model": model, "nproc": nproc, "usable_cpus": usable}
+    for name, (XT, r) in (("C1", W.c1_inputs()), ("C2", W.c2_inputs())):
+        macs, t0, t1 = _cpu_hybrid(name, XT, r, 0, 1 << 30, W.seeds(name), W.seeds(name)["enc"])
+        res[name] = {"shape": f"{XT.shape[0]}x{XT.shape[1]}", "macs": macs, "s": t1 - t0,
+                     "mac_per_s": macs / (t1 - t0), "threads": 1, "kind": "full"}
+        log(f"[cpu-full] {name}: {macs:.3g} MACs in {t1 - t0:.2f} s on 1 thread")
+    H, Wm, delta = W.c4_inputs()
+    for part, A, B in (("forward", H, Wm), ("backward", delta, np.ascontiguousarray(Wm.T))):
+        macs, dt, pack = _cpu_ctmat(A, B, W.seeds("C4"))
+        res[f"C4_{part}"] = {"shape": f"[[{A.shape[0]}x{A.shape[1]}]] x {B.shape[0]}x{B.shape[1]}", "pack": pack,
+                             "macs": macs, "s": dt, "mac_per_s": macs / dt, "threads": 1, "kind": "full"}
+        log(f"[cpu-full] C4 {part}: {macs:.3g} MACs in {dt:.2f} s on 1 thread")
+    shapes = W.c3_shapes(64)
+    seeds = W.seeds("C3")
+    from oracle import oracle as O
+    slots = O.Params.from_dict(W.params_dict("C3")).slots
+    # tasks of at most 64 diagonals of one product, so that no product's
+    # diagonals line up on one worker; each task encrypts r_k, accumulates its
+    # diagonals, and ModDowns and decrypts its partial result
+    tasks = []
+    for k, sh in enumerate(shapes):
+        mp_k = PL.HybridPlan(*sh, slots).mprime
+        tasks += [(k, sh, d0, min(d0 + 64, mp_k)) for d0 in range(0, mp_k, 64)]
+    workers = max(1, min(max_workers, usable))
+    from concurrent.futures import as_completed
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_cpu_worker_ready, range(workers)))
+        futs = [ex.submit(_cpu_c3_range, k, sh, d0, d1, seeds) for (k, sh, d0, d1) in tasks]
+        out = []
+        for f in as_completed(futs):
+            out.append(f.result())
+            if len(out) % 16 == 0:
+                log(f"[cpu-full] C3: {len(out)}/{len(futs)} tasks done")
+    macs = sum(o[0] for o in out)
+    span = max(o[2] for o in out) - min(o[1] for o in out)
+    res["C3"] = {"shape": f"64 products in {len(tasks)} tasks of at most 64 diagonals", "macs": macs, "s": span,
+                 "mac_per_s": macs / span, "threads": workers, "kind": "full"}
+    log(f"[cpu-full] C3: {macs:.3g} MACs in {span:.1f} s on {workers} processes")
+    XT, R = W.c5_inputs(cols=[0])
+    log("[cpu-full] C5 (truncated) ...")
+    macs, t0, t1 = _cpu_hybrid("C5", XT, np.ascontiguousarray(R[:, 0]), 0, 64, W.seeds("C5"), W.seeds("C5")["enc"])
+    res["C5"] = {"shape": f"{XT.shape[0]}x{XT.shape[1]} times one column, first 64 of 2048 diagonals",
+                 "macs": macs, "s": t1 - t0, "mac_per_s": macs / (t1 - t0), "threads": 1,
+                 "kind": "truncated (a per-diagonal extrapolation when applied to the whole job)"}
+    log(f"[cpu-full] C5 (truncated): {macs:.3g} MACs in {t1 - t0:.2f} s on 1 thread")
+    return res
 
 
 def ctmat_c4(reps: int = 5) -> dict:
@@ -283,12 +382,18 @@ def main():
     ap.add_argument("--percall-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (for scaling the HBM byte counters)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only time the CPU oracle on whole configurations (C1-C4 in full, C5 truncated); "
+                         "several minutes on 16 cores")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.cpu_full:
+        print(json.dumps({"cpu_full": cpu_full()}), flush=True)
         return
 
     import torch
