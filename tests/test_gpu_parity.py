@@ -205,6 +205,19 @@ def test_hybrid_c1_bit_exact_and_precise(lazy):
     assert err < (2.0 ** -20 if lazy else 2.0 ** -18)
 
 
+@pytest.mark.parametrize("lazy", [True, False])
+def test_hybrid_c2_full_size_bit_exact_and_precise(lazy):
+    """C2's own product, X^T (256 x 1024) [[r]] at N = 2^13 (m' = 64, 63
+    hoisted rotations), with lazy and with eager ModDown"""
+    XT, r = W.c2_inputs()
+    prm, s, outs, oplan = run_hybrid_both("C2", XT, r, lazy)
+    assert oplan.mprime == 64
+    z = O.decrypt_decode(prm, s, outs[0], prm.scale ** 2)
+    got = PL.hybrid_lazy_ras(oplan, [z])
+    err = np.linalg.norm(got - XT @ r) / np.linalg.norm(XT @ r)
+    assert err < (2.0 ** -20 if lazy else 2.0 ** -18)
+
+
 @pytest.mark.parametrize("m,n", [(4096, 4), (4, 4096), (100, 37), (1, 1)])
 def test_hybrid_partition_and_ragged(m, n):
     rng = np.random.default_rng(m + n)

@@ -318,3 +318,42 @@ def test_c5_large_job_configuration_truncated_sample():
     for c, p in enumerate(cols):
         got = export_ct(ctx, prm.L, p.out, 1)
         assert_cts_equal(got, p.oracle(prm, okeys), f"C5 column {c} d={d}")
+
+
+# ---------------------------------------------------------------------------
+# Alg. 3 at C4 in full, in the benchmark's launch configuration
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("part", ["forward", "backward"])
+def test_c4_ctmat_full_size_bit_exact(part):
+    """[[H]] (256 x 64) W (64 x 256) and the backward [[delta]] (256 x 256)
+    W^T (256 x 64) at C4 (6 + 3 primes) with the widest column packing
+    (pack 32), as the benchmark runs them: every output ciphertext bit-equal
+    to the oracle's on every residue (Sec. 5.3, Alg. 3)."""
+    from concurrent.futures import ThreadPoolExecutor
+    prm, ctx, sk, s = setup("C4")
+    N, lv = prm.N, prm.L
+    H, Wm, delta = W.c4_inputs()
+    A, B = (H, Wm) if part == "forward" else (delta, np.ascontiguousarray(Wm.T))
+    m, n = A.shape
+    nout = B.shape[1]
+    pack = prm.slots // max(m, n)
+    plan = ctx.plan(pvfl.PLAN_CTMAT, m, n, n_out=nout, pack=pack)
+    oplan = PL.CtMatPlan(m, n, nout, prm.slots, pack)
+    assert (plan.info["ct_in"], plan.info["ct_out"], plan.info["n_pts"]) == (oplan.ndiag, oplan.n_out_cts, oplan.n_pts)
+    with ThreadPoolExecutor(WORKERS) as ex:
+        msgs = list(ex.map(lambda i: O.encode(PL.ctmat_ct_slots(oplan, A, i), N, prm.scale), range(oplan.ndiag)))
+        pts = list(ex.map(lambda ik: O.encode(PL.ctmat_pt_slots(oplan, B, ik[0], ik[1]), N, prm.scale),
+                          [(i, k) for i in range(oplan.ndiag) for k in range(oplan.n_out_cts)]))
+        octs = list(ex.map(lambda i: O.encrypt(prm, s, msgs[i], lv, SEED_ENC + i), range(oplan.ndiag)))
+    Q = 2 * (lv + 1) * N
+    ct = dev_f64(plan.bytes("ct_in") // 8)
+    for i in range(oplan.ndiag):
+        one = dev_f64(Q)
+        ctx.encrypt_coeffs(sk, lv, dev_i64(msgs[i]), SEED_ENC + i, one)
+        ct[i * Q:(i + 1) * Q] = one
+    pt = dev_f64(plan.bytes("pt") // 8)
+    ctx.pt_import(lv, False, dev_i64(np.stack(pts)), pt)
+    out = dev_f64(plan.bytes("ct_out") // 8)
+    plan.matmul(ct, pt, None, out)
+    got = export_ct(ctx, lv, out, oplan.n_out_cts)
+    assert_cts_equal(got, PL.ctmat_matmul(prm, oplan, octs, pts), f"C4 {part} [[{m}x{n}]] x {n}x{nout}, pack {pack}")
