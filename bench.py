@@ -541,11 +541,23 @@ def main():
     kd_s = kd["total_ms"] * 1e-3 / max(kd["launches"], 1)
     kd_bytes = kd["bytes"] / max(kd["launches"], 1)
     kd_traffic = measured_traffic(launch_key, KERNEL_SYMBOL["fused_diagonal"])
+    # its arithmetic in FP64 operations (each instruction one): per (product,
+    # rotated diagonal, limb, index) 2 beta key products and the 2 plaintext
+    # products at 6 each (multiply, FMA, multiply, round, FMA, add), 2 (beta - 1)
+    # + 2 additions, and P c0's addition on the Q limbs; diagonal 0 (no
+    # rotation) only its 2 plaintext products and 2 additions
+    lv1, alpha = len(d["q"]), len(d["p"])
+    beta, K = -(-lv1 // alpha), lv1 + alpha
+    elems = binfo["pt_bytes"] / 8
+    elems0 = sum(p.info["row_blocks"] * p.info["col_blocks"] for p in plans) * K * ctx.N
+    kd_ops = (elems - elems0) * (12 * beta + 12 + 2 * (beta - 1) + 2 + lv1 / K) + elems0 * (12 + 2)
     roofline_ks = {"bound": "hbm", "kernel": KERNEL_SYMBOL["fused_diagonal"],
                    "achieved": kd_bytes / kd_s / 1e9 if kd_s > 0 else 0.0, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                    "frac": (kd_bytes / kd_s / 1e9 / HBM_PEAK_GBS) if kd_s > 0 else 0.0, "traffic": kd_traffic,
                    "bytes_per_launch": kd_bytes, "avg_launch_us": kd_s * 1e6,
-                   "traffic_GBps": (kd_traffic / kd_s / 1e9) if (kd_traffic and kd_s > 0) else None}
+                   "traffic_GBps": (kd_traffic / kd_s / 1e9) if (kd_traffic and kd_s > 0) else None,
+                   "fp64_ops_per_launch": kd_ops,
+                   "fp64_op_frac": (kd_ops / kd_s / 1e12 / FP64_OP_PEAK_TOPS) if kd_s > 0 else 0.0}
     ms_percall = None
     if args.percall_steps > 0:
         ms_percall = timed(step_percall, args.percall_steps)
